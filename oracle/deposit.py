@@ -73,7 +73,7 @@ def grid_coords(g, pos):
         x = np.asarray(pos[d], dtype=np.float64)
         xi = (x - g.x0[d]) * g.inv_dx[d]
         i = np.floor(xi)
-        i = np.where(i == g.n[d], g.n[d] - 1, i)
+        i = np.where(xi == g.n[d], g.n[d] - 1, i)
         if np.any((i < 0) | (i >= g.n[d])):
             raise OutOfDomain(f"particle outside the domain along dimension {d}")
         xis.append(xi)

@@ -159,6 +159,13 @@ def test_upper_boundary_clamp_and_errors():
         od.deposit(g, [np.array([4.5]), pos[1], pos[2]], u, w)
     with pytest.raises(od.OutOfDomain):
         od.deposit(g, [np.array([-0.25]), pos[1], pos[2]], u, w)
+    # only xi == n itself is clamped: half a cell beyond the face is outside even where
+    # the stencil would wrap (periodic) and hide it
+    gp = OracleGrid(3, (4, 4, 4), 1)
+    with pytest.raises(od.OutOfDomain):
+        od.grid_coords(gp, [np.array([4.5]), np.array([1.0]), np.array([1.0])])
+    _, cells = od.grid_coords(gp, [np.array([4.0]), np.array([1.0]), np.array([1.0])])
+    assert int(cells[0][0]) == 3
 
 
 def test_2d_c1_shape_partition():
