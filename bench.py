@@ -1,0 +1,209 @@
+"""Benchmark: particles deposited per second, order-3 3D uniform plasma, one MI355X.
+
+Workload (one step, timed end to end): 3D3V uniform plasma, 128^3 cells periodic, 8
+particles per cell (16,777,216), u ~ N(0, 0.05), third-order shapes, dt = 0.2:
+    zero J  ->  pic_deposit(Jx, Jy, Jz; mover detection and the x += v dt drift fused)
+            ->  pic_rebin(AUTO: incremental unless the re-sort policy asks for a full sort)
+Inputs are resident in HBM before timing starts. Prints ONE JSON line.
+
+Also reported (not part of `value`): every deposition path on a static snapshot of the
+same workload (particles/s and rel-L2 against the FP64 oracle measured on the 32^3
+scaled copy), the per-kernel split of the step, the roofline of the deposition kernel
+(algorithmic bytes / measured kernel time / 8 TB/s) and the CPU oracle's rate on a
+bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--path", default="auto")
+    ap.add_argument("--n", type=int, default=128, help="cells per dimension")
+    ap.add_argument("--ppc", type=int, default=8)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design "
+              f"is described in DESIGN.md and not measured.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2601_08277_amd import pic, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n3 = (args.n, args.n, args.n)
+    params, arrays = synth.c2(n=n3, ppc=args.ppc)
+    N = arrays["x"].size
+    ncell = int(np.prod(n3))
+    slack = 0.25
+    grid = pic.Grid(params)
+    nslots = pic.slots_for(N, ncell, slack)
+    parts = pic.Particles.from_arrays(arrays, nslots)
+    bins = pic.Bins(grid, (8, 8, 8), slack, nslots)
+    pic.rebin(grid, parts, bins, pic.REBIN_FULL)
+    J = pic.new_J(grid)
+    path = pic.PATH_NAMES[args.path]
+    flags = pic.F_ACCUMULATE | pic.F_DRIFT | pic.F_EMIT_MOVERS
+    pol = pic.policy()
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        for j in J:
+            j.zero_()
+        if ev:
+            ev[0].record(stream)
+        pic.deposit(grid, parts, bins, path, flags, J=J)
+        if ev:
+            ev[1].record(stream)
+        pic.rebin(grid, parts, bins, pic.REBIN_AUTO, pol)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = N / (ms * 1e-3)
+    st = bins.stats()
+
+    # per-kernel split of the step, HIP events on the launch stream
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for e in evs:
+        step(e)
+    torch.cuda.synchronize()
+    dep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    reb_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    st2 = bins.stats()
+
+    # algorithmic bytes of the fused deposition kernel (per launch)
+    movers = st2["n_moved"]
+    dep_bytes = N * (24 + 12 + 4) + N * 24 + ncell * 24 + movers * 12
+    achieved = dep_bytes / (dep_ms * 1e-3) / 1e9
+    out = {
+        "metric": "particles deposited/s, order-3 3D, split-MFMA vs FP32 at stated err; % roofline",
+        "value": value,
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"uniform plasma {args.n}^3 cells, {args.ppc} per cell, order 3, "
+                               f"periodic, u~N(0,0.05), dt 0.2; step = deposit (fused drift + "
+                               f"mover detection) + incremental rebin",
+                   "particles": int(N), "cells": ncell, "path": args.path, "tile": [8, 8, 8],
+                   "slack": slack},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "deposition (fused drift + mover detection)",
+                     "bytes_per_launch": dep_bytes, "kernel_ms": dep_ms},
+        "breakdown_ms": {"deposit": dep_ms, "rebin": reb_ms,
+                         "other": max(0.0, ms - dep_ms - reb_ms)},
+        "rebin": {"movers_per_step": int(movers), "mover_fraction": movers / N,
+                  "overflow": int(st2["n_overflow"]), "local_rebuilds": int(st2["n_local_rebuilds"]),
+                  "empty_slot_ratio": st2["empty_slot_ratio"], "global_sorts": st2["n_global_sorts"]},
+    }
+    if not args.no_extras:
+        out["paths"] = path_table(pic, torch, grid, parts, bins, N, ncell)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    bins.close()
+    print(json.dumps(out), flush=True)
+
+
+def path_table(pic, torch, grid, parts, bins, N, ncell):
+    """Static deposition (no drift, J accumulated) for every path on the bench snapshot,
+    plus rel-L2 against the FP64 oracle on the 32^3 scaled copy of the workload."""
+    from paper_2601_08277_amd import synth
+    from oracle import deposit as od
+    from oracle.deposit import OracleGrid
+
+    J = pic.new_J(grid)
+    res = {}
+    sp, sa = synth.c2(n=(32, 32, 32))
+    sg = pic.Grid(sp)
+    sN = sa["x"].size
+    s_slots = pic.slots_for(sN, 32 ** 3, 0.25)
+    s_parts = pic.Particles.from_arrays(sa, s_slots)
+    s_bins = pic.Bins(sg, (8, 8, 8), 0.25, s_slots)
+    pic.rebin(sg, s_parts, s_bins, pic.REBIN_FULL)
+    og = OracleGrid.from_params(sp)
+    want = od.deposit(og, [sa["x"], sa["y"], sa["z"]], [sa["ux"], sa["uy"], sa["uz"]], sa["w"])
+    for name in ("atomic", "cell_valu", "mfma_bf16", "mfma_fp16", "unsorted"):
+        try:
+            b = None if name == "unsorted" else bins
+            for _ in range(2):
+                pic.deposit(grid, parts, b, name, pic.F_ACCUMULATE, J=J)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10
+            e0.record()
+            for _ in range(reps):
+                pic.deposit(grid, parts, b, name, pic.F_ACCUMULATE, J=J)
+            e1.record()
+            torch.cuda.synchronize()
+            kms = e0.elapsed_time(e1) / reps
+            byts = N * 40 + ncell * 24
+            Js = pic.deposit(sg, s_parts, None if name == "unsorted" else s_bins, name)
+            torch.cuda.synchronize()
+            err = max(float(np.linalg.norm(Js[c].cpu().numpy() - want[c]) / np.linalg.norm(want[c]))
+                      for c in range(3))
+            res[name] = {"particles_per_s": N / (kms * 1e-3), "kernel_ms": kms,
+                         "hbm_frac": byts / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "rel_l2_vs_oracle_32cubed": err}
+        except Exception as exc:  # a path this build does not provide
+            res[name] = {"error": str(exc)}
+    s_bins.close()
+    return res
+
+
+def cpu_baseline(sample):
+    """The FP64 oracle (as written, untuned) on the first `sample` particles of the
+    workload, one process on the host."""
+    from paper_2601_08277_amd import synth
+    from oracle import deposit as od
+    from oracle.deposit import OracleGrid
+
+    params, arrays = synth.c2()
+    og = OracleGrid.from_params(params)
+    sl = slice(0, sample)
+    t0 = time.perf_counter()
+    od.deposit(og, [arrays["x"][sl], arrays["y"][sl], arrays["z"][sl]],
+               [arrays["ux"][sl], arrays["uy"][sl], arrays["uz"][sl]], arrays["w"][sl])
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample} particles of the 128^3 x 8 workload, full grid, "
+                      f"FP64 NumPy stencil oracle, one process ({dt:.1f} s)",
+            "host_cpus": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,229 @@
+/*
+ * pic.h -- C ABI of libpic, an MI355X (gfx950) library for particle-in-cell current
+ * deposition with cell-sorted particles (MatrixPIC, arXiv 2601.08277).
+ *
+ * What the library computes
+ *   pic_deposit           Eq. 1 (Sec. 3.1): J_c(node) = sum_p q W_p v_{p,c} S(node - x_p),
+ *                         with the separable shape S = s_x s_y s_z of Sec. 4.2.1, B-splines
+ *                         of order 1..3, on a Yee-staggered Jx/Jy/Jz grid, accumulated per
+ *                         cell / per tile ("rhocell", Sec. 3.4, Eq. 4-5) instead of global
+ *                         atomics.
+ *   pic_rebin             keeps particles sorted by cell: the start-up counting sort
+ *                         (GlobalSortParticlesByCell, Alg. 1), the per-step incremental
+ *                         update of movers with gapped bins (Sec. 4.3), local rebuilds and
+ *                         the global re-sort policy (Sec. 4.4).
+ *   pic_deposit_backward  adjoint of pic_deposit: gathers dL/dJ back to the particles and
+ *                         returns dL/dx, dL/du, dL/dw (gather = field interpolation, Sec. 3.1).
+ *   pic_plan_* / pic_deposit_batched
+ *                         many independent patches of uneven size in one persistent launch.
+ *
+ * Conventions (every entry point)
+ *   - Pointers named in pic_particles, J*, G*, d* are DEVICE pointers owned by the caller
+ *     (allocated with hipMalloc or by a framework such as PyTorch). Descriptor structs
+ *     (pic_grid, pic_sort_policy, pic_rebin_stats) are HOST memory, read (or written)
+ *     during the call only.
+ *   - Work is enqueued asynchronously on `stream` (0 = the null stream). Calls neither
+ *     allocate nor synchronise, except pic_bins_create/destroy, pic_plan_create/destroy,
+ *     pic_rebin_stats_read and pic_check, which say so.
+ *   - Argument errors return a negative pic_status at once and enqueue nothing; the
+ *     message is available from pic_last_error() (thread-local). Device-side errors
+ *     (particle out of the domain, non-finite position, capacity) set flags inside the
+ *     bins object; pic_check() / pic_rebin_stats_read() synchronise and report them.
+ *   - Grid arrays (J, G) are float32, x fastest:
+ *        J[((k + gz) * Ny + (j + gy)) * Nx + (i + gx)],  N_d = n_d + 2 g_d,
+ *     g_d = ng on a guard dimension and 0 on a periodic one. In 2D there is no k term.
+ *     Component c sits half a cell along its own axis (Jx at i + 1/2, ...).
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_ERR_INVALID_ARG = -1,       /* bad descriptor, size, pointer or mode            */
+  PIC_ERR_UNSUPPORTED = -2,       /* valid request this build does not implement      */
+  PIC_ERR_OUT_OF_DOMAIN = -3,     /* a particle (or its stencil) left the domain       */
+  PIC_ERR_CAPACITY = -4,          /* particle arrays too small for bins with slack     */
+  PIC_ERR_INVALID_PARTICLE = -5,  /* non-finite position                              */
+  PIC_ERR_HIP = -6                /* a HIP runtime call failed                        */
+} pic_status;
+
+enum { PIC_BC_PERIODIC = 0, PIC_BC_GUARD = 1 };
+
+/* Deposition paths. All accumulate in float32; the split-MFMA paths feed the matrix
+ * cores hi/lo pairs of bf16 or fp16 operands (three products per pair). */
+enum {
+  PIC_PATH_AUTO = 0,         /* pick per order/density (autotuned plan or built-in rule) */
+  PIC_PATH_ATOMIC = 1,       /* one particle per lane, LDS-atomic tile accumulation        */
+  PIC_PATH_CELL_VALU = 2,    /* per-cell register accumulation (rhocell on VALU)           */
+  PIC_PATH_MFMA_BF16 = 3,    /* per-row outer-product contraction on MFMA, split bf16     */
+  PIC_PATH_MFMA_FP16 = 4,    /* same with scaled split fp16                                */
+  PIC_PATH_UNSORTED = 5      /* no bins: one particle per lane, global atomics             */
+};
+
+enum { PIC_REBIN_FULL = 0, PIC_REBIN_INCREMENTAL = 1, PIC_REBIN_AUTO = 2 };
+
+enum {
+  PIC_F_ACCUMULATE = 1u,     /* add into J instead of overwriting it                       */
+  PIC_F_DETERMINISTIC = 2u,  /* reserved; bins are always kept in a deterministic order    */
+  PIC_F_EMIT_MOVERS = 4u,    /* pic_deposit records particles whose cell no longer matches */
+                             /* their bin, for the next PIC_REBIN_INCREMENTAL              */
+  PIC_F_DRIFT = 8u           /* pic_deposit then moves every particle x += v dt (grid dt)  */
+                             /* and records movers against the moved positions            */
+};
+
+#define PIC_INVALID_ID (-1)  /* id of an empty (gap) slot; gap slots also carry w = 0 */
+
+typedef struct {
+  int dim;          /* 2 (x, y) or 3                                              */
+  int n[3];         /* cells per dimension; n[2] = 1 in 2D                        */
+  double x0[3];     /* position of node 0                                         */
+  double dx[3];     /* cell size                                                  */
+  double inv_dx[3]; /* 1 / dx, used as given (the cell index is (x - x0) * inv_dx) */
+  int bc[3];        /* PIC_BC_PERIODIC or PIC_BC_GUARD per dimension               */
+  int ng;           /* guard nodes per side on guard dimensions (>= 1, 2, 2 for   */
+                    /* orders 1, 2, 3)                                            */
+  int order;        /* shape order 1, 2 or 3                                      */
+  float q;          /* charge of the species                                      */
+  double dt;        /* time step of PIC_F_DRIFT and pic_drift                      */
+} pic_grid;
+
+typedef struct {
+  int64_t nslots;   /* length of every array below (slots, valid or gap)          */
+  double *x, *y, *z;/* positions (z unused in 2D but must be a valid pointer)     */
+  float *ux, *uy, *uz; /* proper velocity u = gamma v (c = 1)                     */
+  float *w;         /* macro-particle weight                                      */
+  int32_t *id;      /* particle id, PIC_INVALID_ID in gap slots                    */
+} pic_particles;
+
+typedef struct pic_bins pic_bins;   /* opaque, library-owned device memory */
+typedef struct pic_plan pic_plan;   /* opaque batched-launch plan          */
+
+/* Global re-sort policy, Sec. 4.4; defaults from the parameter table (Appendix A). */
+typedef struct {
+  int min_interval;     /* 10   */
+  int interval;         /* 50   */
+  int rebuild_count;    /* 100  */
+  double empty_ratio;   /* 0.15 */
+  double full_ratio;    /* 0.85 */
+  int perf_enable;      /* 1    */
+  double perf_degrad;   /* 0.80 */
+} pic_sort_policy;
+
+typedef struct {
+  int64_t n_valid;            /* particles held by the bins                          */
+  int64_t n_moved;            /* movers found by the last rebin                       */
+  int64_t n_overflow;         /* movers that found their destination bin full         */
+  int64_t n_mover_drop;       /* movers beyond the mover-list capacity (retried)      */
+  int32_t n_local_rebuilds;   /* tiles rebuilt by the last rebin                       */
+  int32_t n_global_sorts;     /* full sorts since the bins were created               */
+  double empty_slot_ratio;    /* empty slots / slots inside bins                       */
+  int32_t global_sort_recommended; /* policy decision after the last rebin (0/1)      */
+  int32_t last_mode;          /* PIC_REBIN_FULL or PIC_REBIN_INCREMENTAL as executed  */
+  uint32_t error_flags;       /* bit 0 out of domain, bit 1 non-finite, bit 2 capacity */
+} pic_rebin_stats;
+
+/* Default policy values. */
+void pic_sort_policy_default(pic_sort_policy* out);
+
+/* Host-side policy decision of Sec. 4.4 (prioritised triggers 1..5); returns 1 to run a
+ * global sort. `trigger` (nullable) receives the deciding rule number, 0 if none. */
+int pic_policy_decide(const pic_sort_policy* p, int steps_since_sort, int rebuilds_since_sort,
+                      double empty_slot_ratio, double perf, double perf_baseline, int* trigger);
+
+/* Create bins for particles stored in arrays of `nslots` slots. tile[3] is the particle
+ * tile (cells per tile per dimension, tile[2] = 1 in 2D). `slack` is the fraction of
+ * extra slots a full sort gives every cell (at least one per cell). `max_movers`
+ * bounds the mover list (0 = nslots / 8 + 4096). Allocates device memory (synchronous).
+ * Bins hold nothing until the first pic_rebin(PIC_REBIN_FULL). */
+pic_status pic_bins_create(const pic_grid* grid, const int tile[3], double slack,
+                           int64_t nslots, int64_t max_movers, pic_bins** out);
+pic_status pic_bins_destroy(pic_bins* bins);
+
+/* Device views of the bin tables, for inspection and tests. Bins are ordered tile by
+ * tile (tiles x fastest), cells x fastest inside a tile. Bin b owns slots
+ * [off[b], off[b+1]); its first len[b] slots hold its particles, the rest are gaps. */
+typedef struct {
+  int64_t nbins, ntiles;
+  int32_t ntile[3];
+  const int32_t* off;       /* nbins + 1 */
+  const int32_t* len;       /* nbins     */
+  const int32_t* bin_cell;  /* nbins: flat x-fastest cell of every bin */
+} pic_bins_view;
+pic_status pic_bins_get_view(const pic_bins* bins, pic_bins_view* out);
+/* Synchronises `stream` and copies the bin tables to host arrays (each nullable):
+ * off_host nbins + 1 entries, len_host and cell_host nbins entries. */
+pic_status pic_bins_copy_tables(const pic_bins* bins, int32_t* off_host, int32_t* len_host,
+                                int32_t* cell_host, hipStream_t stream);
+
+/* Sort particles into cells. FULL: counting sort of every valid slot into bins with
+ * fresh slack (Alg. 1, GlobalSortParticlesByCell). INCREMENTAL: move only the particles
+ * whose cell changed since the last rebin (Sec. 4.3): insert into the destination bin's
+ * gap slots, compact the source bin, rebuild any tile whose bins overflowed with fresh
+ * uniform gaps. Uses the mover list of the last pic_deposit(PIC_F_EMIT_MOVERS) when it
+ * is fresh, otherwise scans all particles first. A mover that finds no slot stays in its
+ * old bin (deposition still handles it correctly) and is retried next time. AUTO:
+ * INCREMENTAL unless the policy (evaluated on the statistics of an earlier call, without
+ * synchronising) asks for FULL. Particle payload moves between slots; ids travel with it.
+ * `policy` may be NULL (defaults). */
+pic_status pic_rebin(const pic_grid* grid, pic_particles* p, pic_bins* bins, int mode,
+                     const pic_sort_policy* policy, hipStream_t stream);
+
+/* Synchronises `stream` and returns the statistics of the last pic_rebin. */
+pic_status pic_rebin_stats_read(pic_bins* bins, hipStream_t stream, pic_rebin_stats* out);
+
+/* Optional performance sample for policy trigger 5 (higher is better, e.g. particles/s). */
+pic_status pic_bins_report_perf(pic_bins* bins, double perf);
+
+/* Current deposition (Eq. 1). Overwrites Jx, Jy, Jz unless PIC_F_ACCUMULATE. `bins` must
+ * come from pic_rebin on these particles (any path except PIC_PATH_UNSORTED, which
+ * ignores bins and may take NULL). Particles whose cell differs from their bin's cell are
+ * still deposited exactly. With PIC_F_DRIFT the positions are advanced by v dt after
+ * their current is deposited (periodic dimensions wrap). */
+pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bins* bins,
+                       float* Jx, float* Jy, float* Jz, int path, unsigned flags,
+                       hipStream_t stream);
+
+/* Adjoint of pic_deposit for L = sum_c <G_c, J_c>. Writes per slot (gap slots get 0):
+ * dL/dx, dL/dy, dL/dz (dz ignored in 2D; may be NULL there), dL/dux, dL/duy, dL/duz and,
+ * if dw is not NULL, dL/dw. Shape weights are recomputed, not stored. `bins` may be NULL
+ * (particle-parallel gather, no tiles). */
+pic_status pic_deposit_backward(const pic_grid* grid, const pic_particles* p,
+                                const pic_bins* bins, const float* Gx, const float* Gy,
+                                const float* Gz, float* dx, float* dy, float* dz,
+                                float* dux, float* duy, float* duz, float* dw,
+                                unsigned flags, hipStream_t stream);
+
+/* Constant-velocity move of every valid particle, x += v dt (float64), with periodic
+ * wrap: the stand-in for the particle push between steps. */
+pic_status pic_drift(const pic_grid* grid, pic_particles* p, double dt, hipStream_t stream);
+
+/* ---- batched patches ---------------------------------------------------------------
+ * A plan holds `npatch` independent grids and their bins; one persistent kernel pulls
+ * (patch, tile) work items from a device queue, mixing orders and densities. Tile shape
+ * per patch comes from the autotuner cache `tune_cache_json` (host path to a JSON file,
+ * nullable: built-in rule). Allocates device memory (synchronous). */
+pic_status pic_plan_create(const pic_grid* grids, int npatch, pic_bins* const* bins,
+                           const char* tune_cache_json, pic_plan** out);
+pic_status pic_plan_destroy(pic_plan* plan);
+/* particles[k], J3[3k..3k+2] belong to patch k. No allocation, no host round trip:
+ * safe to capture into a hipGraph. */
+pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* particles,
+                               float* const* J3, int path, unsigned flags, hipStream_t stream);
+
+/* Synchronises `stream` and reports the first device-side error recorded in `bins`
+ * (PIC_OK if none); clears the flags. */
+pic_status pic_check(pic_bins* bins, hipStream_t stream);
+
+const char* pic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

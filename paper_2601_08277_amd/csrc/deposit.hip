@@ -1,0 +1,249 @@
+// Current deposition kernels (Eq. 1, Sec. 3.1) for gfx950.
+//
+//  k_dep_unsorted    one particle per lane, global float atomics (no bins; the ablation
+//                    of deposition without sorting).
+//  k_dep_tile_atomic one workgroup per particle tile: particles of the tile's bins are
+//                    read with coalesced loads, their 3 (O+1)^DIM contributions added
+//                    with ds_add_f32 into an LDS window covering the tile plus its stencil
+//                    halo, and the window is added to J once (tile-level reduction, the
+//                    rhocell -> grid step of Eq. 5 at tile granularity). Particles whose
+//                    cell no longer matches their bin are deposited exactly (LDS when the
+//                    stencil fits the window, global atomics otherwise) and, with
+//                    PIC_F_EMIT_MOVERS, listed for the next incremental rebin (the mover
+//                    detection fused into stage 1 of Alg. 2, Sec. 4.3). With PIC_F_DRIFT
+//                    the kernel then advances the position and lists movers against it.
+#include "deposit_common.h"
+
+__device__ uint32_t g_pic_err_nobins;
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+}
+
+uint32_t* nobins_err_ptr() {
+  static uint32_t* ptr = nullptr;
+  if (!ptr) {
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(g_pic_err_nobins)) != hipSuccess) ptr = nullptr;
+  }
+  return ptr;
+}
+
+// -----------------------------------------------------------------------------------
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_dep_unsorted(KGrid G, KPart P, float* __restrict__ J0,
+                                                      float* __restrict__ J1,
+                                                      float* __restrict__ J2, uint32_t* err,
+                                                      int drift, double dt) {
+  const int stride = gridDim.x * blockDim.x;
+  uint32_t bad = 0;
+  float* J[3] = {J0, J1, J2};
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.nslots; s += stride) {
+    if (P.id[s] == PIC_INVALID_ID) continue;
+    double pos[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
+    PartPrep<O, DIM> p;
+    if (!prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad)) continue;
+    float ux = P.ux[s], uy = P.uy[s], uz = P.uz[s];
+    prep_amp(G.q, ux, uy, uz, P.w[s], p.amp);
+    prep_shapes(p);
+    scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
+      int ix = store_idx(G, 0, mx), iy = store_idx(G, 1, my);
+      int iz = DIM == 3 ? store_idx(G, 2, mz) : 0;
+      if ((ix | iy | iz) < 0) {
+        if (v != 0.0f) bad |= PIC_EF_STENCIL;
+        return;
+      }
+      unsafeAtomicAdd(&J[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
+    });
+    if (drift) {
+      drift_one<DIM>(G, pos, ux, uy, uz, dt);
+      P.x[s] = pos[0];
+      P.y[s] = pos[1];
+      if (DIM == 3) P.z[s] = pos[2];
+    }
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// -----------------------------------------------------------------------------------
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_dep_tile_atomic(KGrid G, KBins B, KPart P,
+                                                         float* __restrict__ J0,
+                                                         float* __restrict__ J1,
+                                                         float* __restrict__ J2, unsigned flags,
+                                                         double dt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int t = blockIdx.x;
+  const TileBox tb = tile_box(G.n, B.T, B.nt, t);
+  const TileWin<O, DIM> tw(tb);
+  int32_t* s_off = (int32_t*)smem_raw;
+  int32_t* s_len = s_off + tb.nb + 1;
+  float* win = (float*)(smem_raw + tile_smem_head(B));
+  float* J[3] = {J0, J1, J2};
+
+  for (int i = threadIdx.x; i <= tb.nb; i += blockDim.x) s_off[i] = B.off[tb.b0 + i];
+  for (int i = threadIdx.x; i < tb.nb; i += blockDim.x) s_len[i] = B.len[tb.b0 + i];
+  for (int i = threadIdx.x; i < 3 * tw.size; i += blockDim.x) win[i] = 0.0f;
+  __syncthreads();
+
+  const int S0 = s_off[0], S1 = s_off[tb.nb];
+  const bool emit = flags & PIC_F_EMIT_MOVERS;
+  const bool drift = flags & PIC_F_DRIFT;
+  uint32_t bad = 0;
+  // Strided slot order: in round r thread t takes slot S0 + r + t * rounds, so the lanes
+  // of a wave hold particles of different cells and rarely add to the same LDS word at
+  // once (consecutive slots are mostly the same cell).
+  const int rounds = (S1 - S0 + (int)blockDim.x - 1) / (int)blockDim.x;
+  for (int r = 0; r < rounds; ++r) {
+    const int s = S0 + r + (int)threadIdx.x * rounds;
+    int lb = 0;
+    bool act = s < S1;
+    if (act) {
+      lb = slot_bin(s_off, tb.nb, s);
+      act = s < s_off[lb] + s_len[lb];
+    }
+    PartPrep<O, DIM> p;
+    double pos[3] = {0.0, 0.0, 0.0};
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+    if (act) {
+      pos[0] = P.x[s];
+      pos[1] = P.y[s];
+      if (DIM == 3) pos[2] = P.z[s];
+      act = prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad);
+    }
+    if (act) {
+      ux = P.ux[s];
+      uy = P.uy[s];
+      uz = P.uz[s];
+      prep_amp(G.q, ux, uy, uz, P.w[s], p.amp);
+      prep_shapes(p);
+      if (tw.fits(p)) {
+        scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
+          atomicAdd(&win[tw.index(c, mx, my, mz)], v);
+        });
+      } else {
+        scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
+          int ix = store_idx(G, 0, mx), iy = store_idx(G, 1, my);
+          int iz = DIM == 3 ? store_idx(G, 2, mz) : 0;
+          if ((ix | iy | iz) < 0) {
+            if (v != 0.0f) bad |= PIC_EF_STENCIL;
+            return;
+          }
+          unsafeAtomicAdd(&J[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
+        });
+      }
+    }
+    int32_t newbin = -1;
+    if (act && drift) {
+      drift_one<DIM>(G, pos, ux, uy, uz, dt);
+      P.x[s] = pos[0];
+      P.y[s] = pos[1];
+      if (DIM == 3) P.z[s] = pos[2];
+    }
+    if (emit) {
+      bool mv = false;
+      if (act) {
+        int c2[3];
+        float f2[3];
+        if (prep_cell<DIM>(G, pos[0], pos[1], pos[2], c2, f2, bad)) {
+          newbin = bin_of_cell(G.n, B.T, c2[0], c2[1], c2[2]);
+          mv = newbin != tb.b0 + lb;
+        }
+      }
+      int e = wave_append(mv, &B.ctr[CTR_NMOV]);
+      if (mv) {
+        if (e < B.max_movers) {
+          B.mv_slot[e] = s;
+          B.mv_old[e] = tb.b0 + lb;
+          B.mv_new[e] = newbin;
+        } else {
+          atomicAdd(&B.ctr[CTR_NDROP], 1);
+        }
+      }
+    }
+  }
+  if (bad) atomicOr(B.err, bad);
+  __syncthreads();
+  flush_window<O, DIM>(G, tw, win, J, blockDim.x, threadIdx.x);
+}
+
+// -----------------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(256) void k_drift(KGrid G, KPart P, double dt) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.nslots; s += stride) {
+    if (P.id[s] == PIC_INVALID_ID) continue;
+    double pos[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
+    drift_one<DIM>(G, pos, P.ux[s], P.uy[s], P.uz[s], dt);
+    P.x[s] = pos[0];
+    P.y[s] = pos[1];
+    if (DIM == 3) P.z[s] = pos[2];
+  }
+}
+
+void drift_launch(const KGrid& G, const KPart& P, double dt, hipStream_t s) {
+  if (P.nslots <= 0) return;
+  unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)P.nslots + 255) / 256, 16384);
+  if (G.dim == 3) hipLaunchKernelGGL(k_drift<3>, dim3(blocks), dim3(256), 0, s, G, P, dt);
+  else hipLaunchKernelGGL(k_drift<2>, dim3(blocks), dim3(256), 0, s, G, P, dt);
+}
+
+// -----------------------------------------------------------------------------------
+template <int O, int DIM>
+static void launch_unsorted(const KGrid& G, const KPart& P, float* J0, float* J1, float* J2,
+                            uint32_t* err, bool drift, double dt, hipStream_t s) {
+  unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)P.nslots + 255) / 256, 16384);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_dep_unsorted<O, DIM>), dim3(blocks), dim3(256), 0, s, G, P, J0, J1, J2,
+                     err, drift ? 1 : 0, dt);
+}
+
+template <int O, int DIM>
+static bool launch_tile_atomic(const KGrid& G, const KPart& P, pic_bins* b, float* J0,
+                               float* J1, float* J2, unsigned flags, double dt, hipStream_t s) {
+  size_t smem = tile_smem_head(b->kb) + 3 * sizeof(float) * TileWin<O, DIM>::max_size(b->kb);
+  if (smem > b->max_lds) return false;
+  hipLaunchKernelGGL((k_dep_tile_atomic<O, DIM>), dim3(b->kb.ntiles), dim3(256), smem, s, G,
+                     b->kb, P, J0, J1, J2, flags, dt);
+  return true;
+}
+
+bool deposit_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, float* J1, float* J2,
+                    int path, unsigned flags, double dt, hipStream_t s) {
+  int64_t nJ = (int64_t)G.N[0] * G.N[1] * G.N[2];
+  if (!(flags & PIC_F_ACCUMULATE)) {
+    launch_fill_f32(J0, nJ, 0.0f, s);
+    launch_fill_f32(J1, nJ, 0.0f, s);
+    launch_fill_f32(J2, nJ, 0.0f, s);
+  }
+  if (b && (flags & PIC_F_EMIT_MOVERS)) reset_movers(b, s);
+  const bool drift = flags & PIC_F_DRIFT;
+  if (!b) {
+    uint32_t* err = nobins_err_ptr();
+#define UNS(O_, D_) launch_unsorted<O_, D_>(G, P, J0, J1, J2, err, drift, dt, s)
+    if (G.dim == 3) {
+      if (G.order == 1) UNS(1, 3); else if (G.order == 2) UNS(2, 3); else UNS(3, 3);
+    } else {
+      if (G.order == 1) UNS(1, 2); else if (G.order == 2) UNS(2, 2); else UNS(3, 2);
+    }
+#undef UNS
+    return true;
+  }
+  if (path == PIC_PATH_AUTO) path = choose_path(G, b);
+  if (path == PIC_PATH_CELL_VALU || path == PIC_PATH_MFMA_BF16 || path == PIC_PATH_MFMA_FP16)
+    return deposit_cell_launch(G, P, b, J0, J1, J2, path, flags, dt, s);
+#define TIL(O_, D_) return launch_tile_atomic<O_, D_>(G, P, b, J0, J1, J2, flags, dt, s)
+  if (G.dim == 3) {
+    if (G.order == 1) TIL(1, 3); else if (G.order == 2) TIL(2, 3); else TIL(3, 3);
+  } else {
+    if (G.order == 1) TIL(1, 2); else if (G.order == 2) TIL(2, 2); else TIL(3, 2);
+  }
+#undef TIL
+}

@@ -1,0 +1,70 @@
+// Host-side state of libpic objects and the launchers each kernel file provides.
+#pragma once
+
+#include <string>
+
+#include "pic_internal.h"
+
+// Device counter block: CTR_COUNT int32 counters, the error word, the slot count used by
+// the bins and two 64-bit accumulators, copied to pinned host memory after every rebin.
+struct CtrBlock {
+  int32_t ctr[CTR_COUNT];
+  uint32_t err;
+  int32_t cap_used;           // off[nbins]: slots inside bins
+  unsigned long long desired; // full sort: extra slots wanted
+  unsigned long long pad;
+};
+
+struct pic_bins {
+  pic_grid grid;
+  KBins kb;
+  int64_t nslots;
+  double slack;
+  size_t max_lds = 65536;           // LDS bytes a workgroup may use on this device
+  // device buffers owned by the bins
+  int32_t* bin_cell = nullptr;
+  int32_t* sbin = nullptr;          // full sort: bin of every slot
+  CtrBlock* dctr = nullptr;
+  KPart scratch{};                  // full sort / rebuild staging, nslots slots
+  // scan temporaries (levels of block sums)
+  int32_t* scan_tmp[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t scan_n[5] = {0, 0, 0, 0, 0};
+  int scan_levels = 0;
+  // host-side state
+  bool movers_fresh = false;
+  bool sorted_once = false;
+  CtrBlock* hstats = nullptr;       // pinned
+  hipEvent_t stats_ev = nullptr;
+  bool stats_pending = false;
+  int64_t seq_enqueued = 0, seq_consumed = 0;
+  int last_mode = -1;
+  // policy state (Sec. 4.4)
+  int steps_since_sort = 0;
+  int rebuilds_since_sort = 0;
+  int n_global_sorts = 0;
+  double last_empty_ratio = 0.0;
+  int last_decision = 0;
+  double perf_baseline = -1.0;
+  double perf_last = -1.0;
+  bool perf_baseline_pending = true;
+};
+
+// Launchers (implemented in rebin.hip / deposit.hip / backward.hip).
+KGrid make_kgrid(const pic_grid& g);
+KPart make_kpart(const pic_particles& p);
+void rebin_full(pic_bins* b, const KGrid& G, const KPart& P, hipStream_t s);
+void rebin_incremental(pic_bins* b, const KGrid& G, const KPart& P, hipStream_t s);
+void rebin_finish(pic_bins* b, hipStream_t s);
+bool deposit_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, float* J1,
+                    float* J2, int path, unsigned flags, double dt, hipStream_t s);
+void drift_launch(const KGrid& G, const KPart& P, double dt, hipStream_t s);
+void backward_launch(const KGrid& G, const KPart& P, const pic_bins* b, const float* G0,
+                     const float* G1, const float* G2, float* dx, float* dy, float* dz,
+                     float* dux, float* duy, float* duz, float* dw, hipStream_t s);
+void scan_exclusive_i32(pic_bins* b, int32_t* data, int64_t n, hipStream_t s);
+void reset_movers(pic_bins* b, hipStream_t s);
+void reset_step_counters(pic_bins* b, hipStream_t s);
+
+// Error reporting (api.hip).
+pic_status set_error(pic_status st, const std::string& msg);
+pic_status check_hip(hipError_t e, const char* what);

@@ -1,0 +1,96 @@
+"""CPU checks of the C ABI: the library loads, exports every function pic.h declares, the
+host-side policy agrees with the oracle, and argument errors are reported without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import binning as ob
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic.h")
+LIB = os.path.join(ROOT, "paper_2601_08277_amd", "libpic.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(pic_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB):
+        pytest.fail("libpic.so is not built (run __graft_entry__.build())")
+    from paper_2601_08277_amd import pic
+    return pic.lib()
+
+
+def test_header_declares_core_calls():
+    names = declared_functions()
+    for must in ("pic_deposit", "pic_rebin", "pic_deposit_backward", "pic_bins_create",
+                 "pic_deposit_batched", "pic_plan_create"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in declared_functions():
+        assert hasattr(L, name), f"{name} declared in pic.h but not exported"
+
+
+def test_binding_lists_every_symbol():
+    from paper_2601_08277_amd import pic
+    assert sorted(pic.EXPORTS) == declared_functions()
+
+
+@pytest.mark.parametrize("case", [
+    (3, 500, 0.01, 0.1, 1.0), (50, 0, 0.25, 0.0, 0.0), (20, 101, 0.25, 0.0, 0.0),
+    (20, 100, 0.25, 0.0, 0.0), (20, 0, 0.10, 0.0, 0.0), (20, 0, 0.90, 0.0, 0.0),
+    (20, 0, 0.25, 0.7, 1.0), (20, 0, 0.25, 0.85, 1.0), (10, 0, 0.5, 0.0, 0.0),
+    (49, 0, 0.15, 0.0, 0.0), (49, 0, 0.85, 0.0, 0.0)])
+def test_policy_matches_oracle(L, case):
+    from paper_2601_08277_amd import pic
+    steps, reb, empty, perf, base = case
+    want = ob.should_global_sort(steps, reb, empty, perf if perf > 0 else None,
+                                 base if base > 0 else None)
+    assert pic.policy_decide(steps, reb, empty, perf, base) == want
+
+
+def test_policy_random_agreement(L):
+    from paper_2601_08277_amd import pic
+    rng = np.random.default_rng(0)
+    pol = pic.policy(min_interval=5, interval=30, rebuild_count=7, empty_ratio=0.2,
+                     full_ratio=0.7, perf_enable=1, perf_degrad=0.9)
+    pd = dict(min_interval=5, interval=30, rebuild_count=7, empty_ratio=0.2, full_ratio=0.7,
+              perf_enable=1, perf_degrad=0.9)
+    for _ in range(500):
+        steps = int(rng.integers(0, 40))
+        reb = int(rng.integers(0, 12))
+        empty = float(rng.uniform(0, 1))
+        perf, base = float(rng.uniform(0.5, 1.5)), float(rng.uniform(0.5, 1.5))
+        want = ob.should_global_sort(steps, reb, empty, perf, base, pd)
+        assert pic.policy_decide(steps, reb, empty, perf, base, pol) == want
+
+
+def test_argument_errors_without_gpu(L):
+    from paper_2601_08277_amd import pic
+    g = pic.PicGrid()
+    g.dim = 4
+    h = ctypes.c_void_p()
+    t = (ctypes.c_int * 3)(8, 8, 8)
+    st = L.pic_bins_create(ctypes.byref(g), t, 0.25, 100, 0, ctypes.byref(h))
+    assert st == -1 and b"dim" in L.pic_last_error()
+    g.dim = 3
+    for d in range(3):
+        g.n[d] = 8
+        g.dx[d] = 1.0
+        g.inv_dx[d] = 1.0
+        g.bc[d] = 1
+    g.order = 3
+    g.ng = 1                      # order 3 needs 2 guard nodes
+    st = L.pic_bins_create(ctypes.byref(g), t, 0.25, 100, 0, ctypes.byref(h))
+    assert st == -1 and b"ng" in L.pic_last_error()
+    assert L.pic_deposit(None, None, None, None, None, None, 0, 0, None) == -1

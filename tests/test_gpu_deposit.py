@@ -1,0 +1,146 @@
+"""GPU parity of pic_deposit against the FP64 oracle (element-wise over the whole grid)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import TOL_FP32, TOL_SPLIT, oracle_J, rel_l2, say, setup
+from paper_2601_08277_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+FP32_PATHS = ["unsorted", "atomic", "cell_valu"]
+SPLIT_PATHS = ["mfma_bf16", "mfma_fp16"]
+
+
+def _cases():
+    out = []
+    for order in (1, 2, 3):
+        out.append((f"periodic-20x18x16-o{order}",
+                    lambda o=order: synth.uniform(3, (20, 18, 16), 4, 0.3, o, seed=40 + o)))
+        out.append((f"guard-13x11x9-o{order}",
+                    lambda o=order: synth.uniform(3, (13, 11, 9), 5, 0.3, o, seed=50 + o,
+                                                  bc=(1, 1, 1), ng=3)))
+        out.append((f"2d-30x22-o{order}",
+                    lambda o=order: synth.uniform(2, (30, 22), 6, 0.2, o, seed=60 + o)))
+    out.append(("c1-2d-64x64-o1", synth.c1))
+    out.append(("c2-scaled-32^3-o3", lambda: synth.c2(n=(32, 32, 32))))
+    return out
+
+
+CASES = _cases()
+
+
+def _run(name, make, path, tile=(8, 8, 8)):
+    say(f"case {name} path {path}")
+    from paper_2601_08277_amd import pic
+    params, arrays = make()
+    grid, og, parts, bins = setup(params, arrays, tile=tile)
+    J = pic.deposit(grid, parts, None if path == "unsorted" else bins, path)
+    torch.cuda.synchronize()
+    if path != "unsorted":
+        bins.check()
+    want = oracle_J(og, arrays)
+    errs = [rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)]
+    bins.close()
+    return errs
+
+
+@pytest.mark.parametrize("path", FP32_PATHS)
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_fp32_paths(case, path):
+    errs = _run(case[0], case[1], path)
+    assert max(errs) <= TOL_FP32, errs
+
+
+@pytest.mark.parametrize("path", SPLIT_PATHS)
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_split_paths(case, path):
+    errs = _run(case[0], case[1], path)
+    assert max(errs) <= TOL_SPLIT, errs
+
+
+@pytest.mark.parametrize("tile", [(4, 4, 4), (8, 4, 16), (16, 16, 2), (5, 7, 3)])
+def test_tile_shapes(tile):
+    make = lambda: synth.uniform(3, (21, 17, 12), 6, 0.3, 3, seed=77)
+    for path in ("atomic", "cell_valu", "mfma_bf16"):
+        errs = _run(f"tile{tile}", make, path, tile=tile)
+        tol = TOL_SPLIT if path.startswith("mfma") else TOL_FP32
+        assert max(errs) <= tol, (path, errs)
+
+
+def test_lwfa_shaped_mixed_boundaries():
+    """Scaled laser-wakefield snapshot: periodic x, y; guard z; bubble, sheath, ramp."""
+    say("case lwfa-32x32x128")
+    from paper_2601_08277_amd import pic
+    rng = np.random.default_rng(5)
+    n = (32, 32, 128)
+    counts, sheath = synth.lwfa_counts(n, rng, base_ppc=2.0)
+    params, arrays = synth.uniform(3, n, 1, 0.01, 3, seed=6)   # template, replaced below
+    x, y, z = synth._place(rng, 3, n, counts)
+    N = x.size
+    u = [rng.normal(0, 0.05, N), rng.normal(0, 0.05, N), rng.normal(1.0, 0.5, N)]
+    arrays = synth._finish(rng, x, y, z, u)
+    params = synth._params(3, n, 3, -1.0, (0, 0, 1), 3, 0.2)
+    grid, og, parts, bins = setup(params, arrays)
+    want = oracle_J(og, arrays)
+    for path in ("atomic", "cell_valu", "mfma_bf16", "mfma_fp16"):
+        J = pic.deposit(grid, parts, bins, path)
+        torch.cuda.synchronize()
+        errs = [rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)]
+        tol = TOL_SPLIT if path.startswith("mfma") else TOL_FP32
+        assert max(errs) <= tol, (path, errs)
+    bins.check()
+    bins.close()
+
+
+def test_empty_and_single_particle():
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.uniform(3, (9, 9, 9), 1, 0.1, 3, seed=1)
+    empty = {k: v[:0] for k, v in arrays.items()}
+    grid, og, parts, bins = setup(params, empty)
+    J = pic.deposit(grid, parts, bins, "atomic")
+    torch.cuda.synchronize()
+    assert all(float(j.abs().max()) == 0.0 for j in J)
+    bins.close()
+    one = {k: v[:1].copy() for k, v in arrays.items()}
+    one["x"][:] = 9.0           # exactly on the upper periodic face: clamped cell 8
+    one["y"][:] = 0.0
+    one["z"][:] = 4.5
+    grid, og, parts, bins = setup(params, one)
+    want = oracle_J(og, one)
+    for path in ("unsorted", "atomic", "cell_valu", "mfma_bf16"):
+        J = pic.deposit(grid, parts, None if path == "unsorted" else bins, path)
+        torch.cuda.synchronize()
+        tol = TOL_SPLIT if path.startswith("mfma") else TOL_FP32
+        assert max(rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)) <= tol, path
+    bins.close()
+
+
+def test_accumulate_flag():
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.uniform(3, (12, 12, 12), 3, 0.2, 2, seed=3)
+    grid, og, parts, bins = setup(params, arrays)
+    J = pic.deposit(grid, parts, bins, "atomic")
+    J = pic.deposit(grid, parts, bins, "atomic", flags=pic.F_ACCUMULATE, J=J)
+    torch.cuda.synchronize()
+    want = oracle_J(og, arrays)
+    for c in range(3):
+        assert rel_l2(J[c].cpu().numpy(), 2 * want[c]) <= TOL_FP32
+    bins.close()
+
+
+def test_out_of_domain_and_nan_are_reported():
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.uniform(3, (10, 10, 10), 2, 0.1, 1, seed=2, bc=(1, 1, 1), ng=2)
+    grid, og, parts, bins = setup(params, arrays)
+    parts.x[3] = 10.5            # outside a guard-bounded domain
+    J = pic.deposit(grid, parts, bins, "atomic")
+    with pytest.raises(pic.PicError) as e:
+        bins.check()
+    assert e.value.status == -3
+    parts.x[3] = float("nan")
+    J = pic.deposit(grid, parts, bins, "atomic")
+    with pytest.raises(pic.PicError) as e:
+        bins.check()
+    assert e.value.status == -5
+    bins.close()

@@ -1,0 +1,208 @@
+"""GPU parity of pic_rebin (full and incremental), the drift, and deposition across steps."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import TOL_FP32, check_bins, oracle_J, rel_l2, say, setup
+from oracle import binning as ob
+from oracle import deposit as od
+from paper_2601_08277_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _host(parts):
+    torch.cuda.synchronize()
+    return parts.to_numpy()
+
+
+@pytest.mark.parametrize("name,make,tile", [
+    ("c1", synth.c1, (16, 16, 1)),
+    ("3d-periodic-o3", lambda: synth.uniform(3, (20, 18, 16), 4, 0.3, 3, seed=1), (8, 8, 8)),
+    ("3d-guard-o2", lambda: synth.uniform(3, (13, 11, 9), 5, 0.3, 2, seed=2, bc=(1, 1, 1), ng=3),
+     (4, 8, 3)),
+])
+def test_full_sort(name, make, tile):
+    say(f"case full-sort {name}")
+    params, arrays = make()
+    grid, og, parts, bins = setup(params, arrays, tile=tile)
+    off, ln, bc = bins.tables()
+    check_bins(og, _host(parts), off, ln, bc, ref_arrays=arrays)
+    st = bins.stats()
+    assert st["n_valid"] == arrays["x"].size and st["error_flags"] == 0
+    # canonical order: ids increase inside every bin
+    host = _host(parts)
+    for b in np.flatnonzero(ln > 1)[:2000]:
+        seg = host["id"][off[b]:off[b] + ln[b]]
+        assert np.all(np.diff(seg) > 0)
+    bins.close()
+
+
+def test_drift_bitwise():
+    say("case drift")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.c2(n=(24, 24, 24))
+    grid, og, parts, bins = setup(params, arrays, full=False)
+    pic.drift(grid, parts, params["dt"])
+    host = _host(parts)
+    n = arrays["x"].size
+    want = od.drift(og, [arrays["x"], arrays["y"], arrays["z"]],
+                    [arrays["ux"], arrays["uy"], arrays["uz"]], params["dt"])
+    for d, k in enumerate("xyz"):
+        assert np.array_equal(host[k][:n].view(np.uint64), want[d].view(np.uint64)), k
+    bins.close()
+
+
+def _advance_oracle(og, ref, dt):
+    pos = od.drift(og, [ref["x"], ref["y"], ref["z"]], [ref["ux"], ref["uy"], ref["uz"]], dt)
+    out = dict(ref)
+    out["x"], out["y"], out["z"] = pos
+    return out
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_incremental_steps(fused):
+    """C2-shaped run scaled to 24^3: 20 steps of deposit + drift + incremental rebin.
+
+    Slack 2.0 leaves every bin room for the net inflow of 20 steps, so no mover overflows
+    and every step's bins must equal the oracle's sets exactly (overflow handling has
+    its own tests below)."""
+    say(f"case incremental fused={fused}")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.c2(n=(24, 24, 24))
+    grid, og, parts, bins = setup(params, arrays, slack=2.0)
+    ref = dict(arrays)
+    dt = params["dt"]
+    for step in range(20):
+        old_cells = ob.cell_index(og, [ref["x"], ref["y"], ref["z"]])
+        want = oracle_J(og, ref)
+        if fused:
+            J = pic.deposit(grid, parts, bins, "atomic", flags=pic.F_DRIFT | pic.F_EMIT_MOVERS)
+        else:
+            J = pic.deposit(grid, parts, bins, "atomic")
+            pic.drift(grid, parts, dt)
+        errs = [rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)]
+        assert max(errs) <= TOL_FP32, (step, errs)
+        ref = _advance_oracle(og, ref, dt)
+        pic.rebin(grid, parts, bins, pic.REBIN_INCREMENTAL)
+        st = bins.stats()
+        n_mov = ob.movers(og, [ref["x"], ref["y"], ref["z"]], ref["id"], old_cells)
+        assert st["n_moved"] == n_mov, (step, st, n_mov)
+        assert 0.005 < n_mov / ref["id"].size < 0.05
+        off, ln, bc = bins.tables()
+        if st["n_overflow"]:
+            host = _host(parts)
+            from gpu_util import dense_slots
+            sl, b = dense_slots(off, ln)
+            cell = ob.cell_index(og, [host["x"][sl], host["y"][sl], host["z"][sl]])
+            bad = np.flatnonzero(cell != bc[b])
+            inv = np.empty_like(bc)
+            inv[bc] = np.arange(bc.size)
+            for q in bad[:4]:
+                nb = inv[cell[q]]
+                say(f"step {step} stale id {host['id'][sl[q]]} slot {sl[q]} bin {b[q]} -> "
+                    f"cell {cell[q]} bin {nb} len {ln[nb]} cap {off[nb + 1] - off[nb]}")
+        assert st["n_overflow"] == 0 and st["error_flags"] == 0, (step, st)
+        check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref)
+    bins.close()
+
+
+def test_overflow_rebuild_and_stale_particles():
+    """Tight slack: inserts overflow, tiles are rebuilt, stale particles still deposit
+    exactly, and the bins converge to the oracle's sets."""
+    say("case overflow")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.uniform(3, (16, 16, 16), 4, 0.6, 3, seed=9, dt=0.5)
+    grid, og, parts, bins = setup(params, arrays, slack=0.0, max_movers=1 << 20)
+    ref = dict(arrays)
+    saw_overflow = saw_rebuild = False
+    for step in range(6):
+        want = oracle_J(og, ref)
+        J = pic.deposit(grid, parts, bins, "atomic", flags=pic.F_DRIFT | pic.F_EMIT_MOVERS)
+        errs = [rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)]
+        assert max(errs) <= TOL_FP32, (step, errs)
+        ref = _advance_oracle(og, ref, params["dt"])
+        pic.rebin(grid, parts, bins, pic.REBIN_INCREMENTAL)
+        st = bins.stats()
+        saw_overflow |= st["n_overflow"] > 0
+        saw_rebuild |= st["n_local_rebuilds"] > 0
+        off, ln, bc = bins.tables()
+        assert st["n_mover_drop"] == 0
+        stale = check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref,
+                           stale_ok=int(st["n_overflow"]))
+        assert stale == st["n_overflow"]
+    assert saw_overflow
+    # a full sort restores exact bins
+    pic.rebin(grid, parts, bins, pic.REBIN_FULL)
+    off, ln, bc = bins.tables()
+    check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref)
+    bins.close()
+
+
+def test_local_rebuild_frees_slots():
+    """Slack only in some bins: a tile rebuild spreads the free slots and later inserts fit."""
+    say("case rebuild")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.uniform(3, (16, 16, 16), 6, 0.4, 1, seed=4, dt=0.5)
+    grid, og, parts, bins = setup(params, arrays, slack=0.2, max_movers=1 << 20)
+    ref = dict(arrays)
+    rebuilds = 0
+    for step in range(8):
+        J = pic.deposit(grid, parts, bins, "atomic", flags=pic.F_DRIFT | pic.F_EMIT_MOVERS)
+        ref = _advance_oracle(og, ref, params["dt"])
+        pic.rebin(grid, parts, bins, pic.REBIN_INCREMENTAL)
+        st = bins.stats()
+        rebuilds += st["n_local_rebuilds"]
+        off, ln, bc = bins.tables()
+        stale = check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref,
+                           stale_ok=int(st["n_overflow"]))
+        assert stale == st["n_overflow"]
+    want = oracle_J(og, ref)
+    J = pic.deposit(grid, parts, bins, "atomic")
+    assert max(rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)) <= TOL_FP32
+    assert rebuilds > 0
+    bins.close()
+
+
+def test_auto_policy_runs_full_sort():
+    say("case auto-policy")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.c2(n=(16, 16, 16))
+    grid, og, parts, bins = setup(params, arrays)
+    pol = pic.policy(min_interval=1, interval=3, perf_enable=0)
+    modes = []
+    for step in range(7):
+        pic.deposit(grid, parts, bins, "atomic", flags=pic.F_DRIFT | pic.F_EMIT_MOVERS)
+        pic.rebin(grid, parts, bins, pic.REBIN_AUTO, pol)
+        modes.append(bins.stats()["last_mode"])
+    assert pic.REBIN_FULL in modes[2:] and modes[0] == pic.REBIN_INCREMENTAL
+    bins.close()
+
+
+def test_mover_list_capacity_drop_is_retried():
+    """A mover list too small for one step drops entries; they stay in their old bins,
+    deposit exactly, and later rebins pick them up."""
+    say("case mover drop")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.uniform(3, (12, 12, 12), 6, 0.5, 2, seed=12, dt=0.5)
+    grid, og, parts, bins = setup(params, arrays, slack=1.0, max_movers=256)
+    ref = dict(arrays)
+    J = pic.deposit(grid, parts, bins, "atomic", flags=pic.F_DRIFT | pic.F_EMIT_MOVERS)
+    ref = _advance_oracle(og, ref, params["dt"])
+    pic.rebin(grid, parts, bins, pic.REBIN_INCREMENTAL)
+    st = bins.stats()
+    assert st["n_mover_drop"] > 0 and st["n_moved"] == 256
+    off, ln, bc = bins.tables()
+    stale = check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref,
+                       stale_ok=int(st["n_overflow"] + st["n_mover_drop"]))
+    assert stale == st["n_overflow"] + st["n_mover_drop"]
+    want = oracle_J(og, ref)
+    J = pic.deposit(grid, parts, bins, "atomic")
+    assert max(rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)) <= TOL_FP32
+    for _ in range(40):          # without further motion the backlog drains
+        pic.rebin(grid, parts, bins, pic.REBIN_INCREMENTAL)
+        if bins.stats()["n_moved"] == 0:
+            break
+    off, ln, bc = bins.tables()
+    check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref)
+    bins.close()
