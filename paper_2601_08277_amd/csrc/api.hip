@@ -157,6 +157,7 @@ static void free_bins(pic_bins* b) {
   for (int32_t* p : bufs)
     if (p) (void)hipFree(p);
   if (b->dctr) (void)hipFree(b->dctr);
+  if (b->kb.wscr) (void)hipFree(b->kb.wscr);
   void* sp[] = {b->scratch.x, b->scratch.y, b->scratch.z, b->scratch.ux, b->scratch.uy,
                 b->scratch.uz, b->scratch.w};
   for (void* p : sp)
@@ -192,6 +193,9 @@ extern "C" pic_status pic_bins_create(const pic_grid* grid, const int tile[3], d
   }
   if ((int64_t)T[0] * T[1] * T[2] > 8192)
     return set_error(PIC_ERR_INVALID_ARG, "a tile may hold at most 8192 cells");
+  for (int d = 0; d < grid->dim; ++d)
+    if (T[d] < 4 && T[d] != n[d])
+      return set_error(PIC_ERR_INVALID_ARG, "tile extents must be at least 4 cells (or the grid)");
   if (nbins >= (1ll << 31) - 1) return set_error(PIC_ERR_INVALID_ARG, "too many cells");
   if (max_movers <= 0) max_movers = nslots / 8 + 4096;
   if (max_movers >= (1ll << 31)) max_movers = (1ll << 31) - 1;
@@ -222,6 +226,12 @@ extern "C" pic_status pic_bins_create(const pic_grid* grid, const int tile[3], d
   A(dalloc(&b->bin_cell, nbins));
   A(dalloc(&b->sbin, nslots));
   A(dalloc(&b->dctr, 1));
+  {
+    int64_t wm = 1;
+    for (int d = 0; d < grid->dim; ++d) wm *= T[d] + 4;
+    b->kb.wmax = (int32_t)wm;
+    A(dalloc(&b->kb.wscr, ntiles * 3 * wm));
+  }
   A(dalloc(&b->scratch.x, nslots));
   A(dalloc(&b->scratch.y, nslots));
   A(dalloc(&b->scratch.z, nslots));

@@ -5,8 +5,9 @@
 //  k_dep_tile_atomic one workgroup per particle tile: particles of the tile's bins are
 //                    read with coalesced loads, their 3 (O+1)^DIM contributions added
 //                    with ds_add_f32 into an LDS window covering the tile plus its stencil
-//                    halo, and the window is added to J once (tile-level reduction, the
-//                    rhocell -> grid step of Eq. 5 at tile granularity). Particles whose
+//                    halo, and the window is stored once (tile-level reduction, the
+//                    rhocell -> grid step of Eq. 5 at tile granularity); k_halo_sum then
+//                    adds the overlapping windows of neighbouring tiles into J. Particles whose
 //                    cell no longer matches their bin are deposited exactly (LDS when the
 //                    stencil fits the window, global atomics otherwise) and, with
 //                    PIC_F_EMIT_MOVERS, listed for the next incremental rebin (the mover
@@ -171,7 +172,75 @@ __global__ __launch_bounds__(256) void k_dep_tile_atomic(KGrid G, KBins B, KPart
   }
   if (bad) atomicOr(B.err, bad);
   __syncthreads();
-  flush_window<O, DIM>(G, tw, win, J, blockDim.x, threadIdx.x);
+  store_window<O, DIM>(B, t, tw, win, blockDim.x, threadIdx.x);
+}
+
+// J += sum of the stored tile windows covering each node (at most 2 tiles per
+// dimension for tiles at least as wide as the stencil reach). One thread per node, all
+// three components.
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_halo_sum(KGrid G, KBins B, float* __restrict__ J0,
+                                                  float* __restrict__ J1,
+                                                  float* __restrict__ J2) {
+  constexpr int LO = TileWin<O, DIM>::LO, R = TileWin<O, DIM>::R;
+  const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride) {
+    const int n3[3] = {(int)(idx % G.N[0]), (int)((idx / G.N[0]) % G.N[1]),
+                       (int)(idx / ((int64_t)G.N[0] * G.N[1]))};
+    int tl[3][6], wl[3][6], cnt[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      cnt[d] = 0;
+      if (d >= DIM) {
+        tl[d][0] = 0;
+        wl[d][0] = 0;
+        cnt[d] = 1;
+        continue;
+      }
+      if (G.per[d]) {
+        for (int k = -1; k <= 1; ++k)
+          cnt[d] = halo_cands(n3[d] + k * G.n[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d],
+                              cnt[d]);
+      } else {
+        cnt[d] = halo_cands(n3[d] - G.g[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d], cnt[d]);
+      }
+    }
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int a = 0; a < cnt[2]; ++a)
+      for (int b = 0; b < cnt[1]; ++b)
+        for (int c = 0; c < cnt[0]; ++c) {
+          const int t = tl[0][c] + B.nt[0] * (tl[1][b] + B.nt[1] * tl[2][a]);
+          const int W0 = min(B.T[0], G.n[0] - tl[0][c] * B.T[0]) + R;
+          const int W1 = DIM >= 2 ? min(B.T[1], G.n[1] - tl[1][b] * B.T[1]) + R : 1;
+          const int li = (wl[2][a] * W1 + wl[1][b]) * W0 + wl[0][c];
+          const float* src = B.wscr + (int64_t)t * 3 * B.wmax + li;
+          s0 += src[0];
+          s1 += src[B.wmax];
+          s2 += src[2 * B.wmax];
+        }
+    J0[idx] += s0;
+    J1[idx] += s1;
+    J2[idx] += s2;
+  }
+}
+
+template <int O, int DIM>
+static void launch_halo(const KGrid& G, pic_bins* b, float* J0, float* J1, float* J2,
+                        hipStream_t s) {
+  const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
+  unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 16384));
+  hipLaunchKernelGGL((k_halo_sum<O, DIM>), dim3(blocks), dim3(256), 0, s, G, b->kb, J0, J1, J2);
+}
+
+void halo_launch(const KGrid& G, pic_bins* b, float* J0, float* J1, float* J2, hipStream_t s) {
+#define HL(O_, D_) launch_halo<O_, D_>(G, b, J0, J1, J2, s)
+  if (G.dim == 3) {
+    if (G.order == 1) HL(1, 3); else if (G.order == 2) HL(2, 3); else HL(3, 3);
+  } else {
+    if (G.order == 1) HL(1, 2); else if (G.order == 2) HL(2, 2); else HL(3, 2);
+  }
+#undef HL
 }
 
 // -----------------------------------------------------------------------------------
@@ -237,13 +306,18 @@ bool deposit_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, floa
     return true;
   }
   if (path == PIC_PATH_AUTO) path = choose_path(G, b);
-  if (path == PIC_PATH_CELL_VALU || path == PIC_PATH_MFMA_BF16 || path == PIC_PATH_MFMA_FP16)
-    return deposit_cell_launch(G, P, b, J0, J1, J2, path, flags, dt, s);
-#define TIL(O_, D_) return launch_tile_atomic<O_, D_>(G, P, b, J0, J1, J2, flags, dt, s)
-  if (G.dim == 3) {
-    if (G.order == 1) TIL(1, 3); else if (G.order == 2) TIL(2, 3); else TIL(3, 3);
+  bool ok = false;
+  if (path == PIC_PATH_CELL_VALU || path == PIC_PATH_MFMA_BF16 || path == PIC_PATH_MFMA_FP16) {
+    ok = deposit_cell_launch(G, P, b, J0, J1, J2, path, flags, dt, s);
   } else {
-    if (G.order == 1) TIL(1, 2); else if (G.order == 2) TIL(2, 2); else TIL(3, 2);
-  }
+#define TIL(O_, D_) ok = launch_tile_atomic<O_, D_>(G, P, b, J0, J1, J2, flags, dt, s)
+    if (G.dim == 3) {
+      if (G.order == 1) TIL(1, 3); else if (G.order == 2) TIL(2, 3); else TIL(3, 3);
+    } else {
+      if (G.order == 1) TIL(1, 2); else if (G.order == 2) TIL(2, 2); else TIL(3, 2);
+    }
 #undef TIL
+  }
+  if (ok) halo_launch(G, b, J0, J1, J2, s);
+  return ok;
 }

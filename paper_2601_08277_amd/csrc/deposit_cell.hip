@@ -1,8 +1,9 @@
 // Per-cell deposition on VALU: the rhocell of Sec. 3.4 (Eq. 4) / Sec. 4.2.1 kept in
 // registers.
 //
-// A workgroup owns one particle tile; each wave owns groups of 64 consecutive cells of
-// the tile (bins are contiguous, so a group's particles are one contiguous slot range).
+// One wave owns one particle tile and walks it in groups of up to 64 consecutive cells of
+// one z-plane of the tile (bins are contiguous, so a group's particles are one
+// contiguous slot range).
 //  stage      lanes = slots, coalesced loads: position -> cell + float32 offset (FP64
 //             only here), amplitude q W v_c, validity; the fused drift and mover
 //             detection (stage 1 of Alg. 2) also run here, once per particle. Offsets and
@@ -11,8 +12,11 @@
 //  accumulate lanes = cells: each lane walks its cell's staged particles and accumulates
 //             the separable outer product (amp_c s_x) (x) s_y (x) s_z on the cell's padded
 //             stencil window in registers (Eq. 4).
-//  flush      once per cell: the window is added to the tile's LDS window (Eq. 5), and
-//             the tile window to J once per tile.
+//  flush      once per cell, into the tile's LDS window (Eq. 5). Within one instruction
+//             every lane adds at the same offset from its own cell, so the 64 addresses
+//             differ and a plain read-add-write is race free; LDS float atomics, which
+//             cost about 190 LDS cycles per wave instruction on this part, are not used.
+//             The tile window is stored once and k_halo_sum adds neighbouring windows.
 // Staggered axes use a window one node wider than the stencil (the stencil of a particle
 // in cell i starts at i + lo or i + lo + 1 depending on which half of the cell it is in);
 // the extra node carries a zero weight. Order 3 in 3D needs 3 x 80 accumulators; they are
@@ -52,7 +56,7 @@ __device__ __forceinline__ int wave_max(int v) {
 
 constexpr int CV_GROUP = 64;    // cells per wave group
 constexpr int CV_CAP = 512;     // staged slots per wave per round
-constexpr int CV_WAVES = 4;
+constexpr int CV_WAVES = 1;
 
 // Per-wave staging area (SoA): offsets and amplitudes of CV_CAP slots.
 struct Stage {
@@ -106,23 +110,17 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
       mine = p.cell[0] == tb.c0[0] + cx && p.cell[1] == tb.c0[1] + cy &&
              (DIM == 2 || p.cell[2] == tb.c0[2] + cz);
       if (!mine && LAST) {
-        // stale particle: exact per-particle path, all components, once
+        // stale particle: exact per-particle path (global atomics), all components, once
         prep_shapes(p);
-        if (tw.fits(p)) {
-          scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
-            atomicAdd(&win[tw.index(c, mx, my, mz)], v);
-          });
-        } else {
-          scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
-            int ix = store_idx(G, 0, mx), iy = store_idx(G, 1, my);
-            int iz = DIM == 3 ? store_idx(G, 2, mz) : 0;
-            if ((ix | iy | iz) < 0) {
-              if (v != 0.0f) bad |= PIC_EF_STENCIL;
-              return;
-            }
-            unsafeAtomicAdd(&J[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
-          });
-        }
+        scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
+          int ix = store_idx(G, 0, mx), iy = store_idx(G, 1, my);
+          int iz = DIM == 3 ? store_idx(G, 2, mz) : 0;
+          if ((ix | iy | iz) < 0) {
+            if (v != 0.0f) bad |= PIC_EF_STENCIL;
+            return;
+          }
+          unsafeAtomicAdd(&J[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
+        });
       }
     }
     if (s < hi) {
@@ -228,10 +226,14 @@ __device__ __forceinline__ void cv_accumulate(const int32_t* s_off, const int32_
   (void)NA;
 }
 
-// Add the cell's accumulators to the tile window.
+// Add the cell's accumulators to the tile window with plain read-add-write. All cells of
+// a group lie in one z-plane of the tile, so two lanes can only meet on a window node
+// through offsets that differ in x or y: the z-column of one (c, ix, iy) offset is read,
+// added and written as a batch, and a compiler barrier keeps the next column's reads
+// behind this column's writes (LDS executes a wave's instructions in order).
 template <int O, int DIM, int CB, int CE>
 __device__ __forceinline__ void cv_flush(const TileWin<O, DIM>& tw, const int* cc,
-                                         const float* acc, float* win) {
+                                         const float* acc, float* win, bool own) {
   constexpr int A0 = acc_off<O, DIM>(CB);
 #pragma unroll
   for (int c = CB; c < CE; ++c) {
@@ -241,14 +243,20 @@ __device__ __forceinline__ void cv_flush(const TileWin<O, DIM>& tw, const int* c
     const int lz = DIM == 3 ? cc[2] + win_lo(O, c == 2) : 0;
     const int base = acc_off<O, DIM>(c) - A0;
 #pragma unroll
-    for (int iz = 0; iz < WZ; ++iz)
+    for (int iy = 0; iy < WY; ++iy)
 #pragma unroll
-      for (int iy = 0; iy < WY; ++iy)
+      for (int ix = 0; ix < WX; ++ix) {
+        if (own) {
+          float v[5];
 #pragma unroll
-        for (int ix = 0; ix < WX; ++ix) {
-          const float v = acc[base + (iz * WY + iy) * WX + ix];
-          if (v != 0.0f) atomicAdd(&win[tw.index(c, lx + ix, ly + iy, lz + iz)], v);
+          for (int iz = 0; iz < WZ; ++iz) v[iz] = win[tw.index(c, lx + ix, ly + iy, lz + iz)];
+#pragma unroll
+          for (int iz = 0; iz < WZ; ++iz)
+            win[tw.index(c, lx + ix, ly + iy, lz + iz)] =
+                v[iz] + acc[base + (iz * WY + iy) * WX + ix];
         }
+        asm volatile("" ::: "memory");
+      }
   }
 }
 
@@ -288,7 +296,7 @@ __device__ __forceinline__ void cv_pass(const KGrid& G, const KBins& B, const KP
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if (own && s_len[cell] > 0) cv_flush<O, DIM, CB, CE>(tw, cc, acc, win);
+  cv_flush<O, DIM, CB, CE>(tw, cc, acc, win, own && s_len[cell] > 0);
 }
 
 template <int O, int DIM>
@@ -310,8 +318,12 @@ __global__ __launch_bounds__(CV_WAVES * PIC_WAVE) void k_dep_cell_valu(
   uint32_t bad = 0;
   const int wave = threadIdx.x / PIC_WAVE;
   Stage& st = stage[wave];
-  for (int g0 = wave * CV_GROUP; g0 < tb.nb; g0 += CV_WAVES * CV_GROUP) {
-    const int gn = min(CV_GROUP, tb.nb - g0);
+  const int exy = tb.e[0] * tb.e[1];
+  const int per_plane = (exy + CV_GROUP - 1) / CV_GROUP;
+  for (int gi = wave; gi < per_plane * tb.e[2]; gi += CV_WAVES) {
+    const int pz = gi / per_plane;
+    const int g0 = pz * exy + (gi - pz * per_plane) * CV_GROUP;
+    const int gn = min(CV_GROUP, (pz + 1) * exy - g0);
     if constexpr (O == 3 && DIM == 3) {
       cv_pass<O, DIM, 0, 2, false>(G, B, P, tb, tw, s_off, s_len, g0, gn, st, win, J, flags, dt, bad);
       cv_pass<O, DIM, 2, 3, true>(G, B, P, tb, tw, s_off, s_len, g0, gn, st, win, J, flags, dt, bad);
@@ -321,7 +333,7 @@ __global__ __launch_bounds__(CV_WAVES * PIC_WAVE) void k_dep_cell_valu(
   }
   if (bad) atomicOr(B.err, bad);
   __syncthreads();
-  flush_window<O, DIM>(G, tw, win, J, blockDim.x, threadIdx.x);
+  store_window<O, DIM>(B, blockIdx.x, tw, win, blockDim.x, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------------

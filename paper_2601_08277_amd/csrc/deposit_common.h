@@ -72,26 +72,34 @@ __device__ __forceinline__ int slot_bin(const int32_t* s_off, int nb, int s) {
   return lo;
 }
 
-// Add the tile's window to J (float atomics: windows of neighbouring tiles overlap).
+// Store the tile's window to its slab of the window scratch (plain coalesced stores);
+// k_halo_sum then adds the overlapping windows of neighbouring tiles into J, so no
+// global atomics are needed (and the sum is deterministic).
 template <int O, int DIM>
-__device__ __forceinline__ void flush_window(const KGrid& G, const TileWin<O, DIM>& tw,
-                                             const float* win, float* const* J, int nthr,
-                                             int tid) {
-  const int W0 = tw.W[0], W01 = tw.W[0] * tw.W[1];
-  for (int i = tid; i < 3 * tw.size; i += nthr) {
-    float v = win[i];
-    if (v == 0.0f) continue;
-    int c = i / tw.size;
-    int r = i - c * tw.size;
-    int z = r / W01;
-    int y = (r - z * W01) / W0;
-    int x = r - z * W01 - y * W0;
-    int ix = store_idx(G, 0, tw.o[0] + x);
-    int iy = store_idx(G, 1, tw.o[1] + y);
-    int iz = DIM == 3 ? store_idx(G, 2, tw.o[2] + z) : 0;
-    if ((ix | iy | iz) < 0) continue;
-    unsafeAtomicAdd(&J[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
+__device__ __forceinline__ void store_window(const KBins& B, int tile, const TileWin<O, DIM>& tw,
+                                             const float* win, int nthr, int tid) {
+  float* dst = B.wscr + (int64_t)tile * 3 * B.wmax;
+  for (int c = 0; c < 3; ++c)
+    for (int i = tid; i < tw.size; i += nthr) dst[(int64_t)c * B.wmax + i] = win[c * tw.size + i];
+}
+
+// Window of the tiles along one dimension that contain unwrapped node m:
+// appends (tile, index inside the window) pairs; returns the new count.
+__device__ __forceinline__ int halo_cands(int m, int n, int T, int nt, int LO, int R, int* tl,
+                                          int* wl, int cnt) {
+  int th = (m - LO) >= 0 ? (m - LO) / T : -((LO - m + T - 1) / T);
+  for (int t = th; t >= 0 && t >= th - 2; --t) {
+    if (t >= nt) continue;
+    int c0 = t * T;
+    int e = min(T, n - c0);
+    int w0 = c0 + LO;
+    if (m >= w0 && m < w0 + e + R && cnt < 6) {
+      tl[cnt] = t;
+      wl[cnt] = m - w0;
+      ++cnt;
+    }
   }
+  return cnt;
 }
 
 // Path selection and the per-cell paths (deposit_cell.hip).

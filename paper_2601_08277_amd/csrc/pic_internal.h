@@ -67,6 +67,8 @@ struct KBins {
   int32_t max_movers;
   int32_t* ctr;       // CTR_COUNT
   uint32_t* err;
+  float* wscr;        // per-tile stencil windows: ntiles x 3 x wmax floats
+  int32_t wmax;       // window floats per component reserved per tile
 };
 
 // ---------------------------------------------------------------------------------

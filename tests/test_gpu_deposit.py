@@ -59,7 +59,7 @@ def test_split_paths(case, path):
     assert max(errs) <= TOL_SPLIT, errs
 
 
-@pytest.mark.parametrize("tile", [(4, 4, 4), (8, 4, 16), (16, 16, 2), (5, 7, 3)])
+@pytest.mark.parametrize("tile", [(4, 4, 4), (8, 4, 16), (16, 16, 4), (5, 7, 4)])
 def test_tile_shapes(tile):
     make = lambda: synth.uniform(3, (21, 17, 12), 6, 0.3, 3, seed=77)
     for path in ("atomic", "cell_valu", "mfma_bf16"):

@@ -20,7 +20,7 @@ def _host(parts):
     ("c1", synth.c1, (16, 16, 1)),
     ("3d-periodic-o3", lambda: synth.uniform(3, (20, 18, 16), 4, 0.3, 3, seed=1), (8, 8, 8)),
     ("3d-guard-o2", lambda: synth.uniform(3, (13, 11, 9), 5, 0.3, 2, seed=2, bc=(1, 1, 1), ng=3),
-     (4, 8, 3)),
+     (4, 8, 4)),
 ])
 def test_full_sort(name, make, tile):
     say(f"case full-sort {name}")
