@@ -54,6 +54,97 @@ struct TileWin {
   }
 };
 
+// Window of a slab of the tile: planes [s0, s1) along the slowest used dimension
+// (z in 3D, y in 2D), full extent along the others. A wave that owns a slab accumulates
+// into its own sub-window, so waves never write the same LDS words.
+template <int O, int DIM>
+struct SubWin {
+  static constexpr int SD = DIM - 1;
+  int o[3];
+  int W[3];
+  int size;
+  int s0;
+  __device__ __forceinline__ SubWin(const TileWin<O, DIM>& tw, int s0_, int s1_) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      o[d] = tw.o[d];
+      W[d] = tw.W[d];
+    }
+    s0 = s0_;
+    o[SD] = tw.c0[SD] + s0_ + TileWin<O, DIM>::LO;
+    W[SD] = (s1_ - s0_) + TileWin<O, DIM>::R;
+    size = W[0] * W[1] * W[2];
+  }
+  __host__ __device__ static int max_size(const KBins& kb, int waves) {
+    int s = 1;
+    for (int d = 0; d < DIM; ++d) {
+      int ext = kb.T[d];
+      if (d == SD) ext = (ext + waves - 1) / waves;
+      s *= ext + TileWin<O, DIM>::R;
+    }
+    return s;
+  }
+  __device__ __forceinline__ int index(int c, int mx, int my, int mz) const {
+    return c * size + ((mz - o[2]) * W[1] + (my - o[1])) * W[0] + (mx - o[0]);
+  }
+};
+
+// Per-wave mover buffer in LDS: movers are appended with a ballot and a lane prefix
+// count (no global atomic per chunk) and copied to the global list, one atomic per
+// flush, when it fills and at the end of the tile.
+constexpr int MBUF = 128;
+
+struct MoverBuf {
+  int32_t* slot;
+  int32_t* oldb;
+  int32_t* newb;
+  int cnt;  // wave-uniform
+};
+
+__device__ __forceinline__ void mb_flush(MoverBuf& mb, const KBins& B) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (mb.cnt > 0) {
+    const int lane = __lane_id();
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&B.ctr[CTR_NMOV], mb.cnt);
+    base = __shfl(base, 0);
+    int drop = 0;
+    for (int i = lane; i < mb.cnt; i += PIC_WAVE) {
+      const int e = base + i;
+      if (e < B.max_movers) {
+        B.mv_slot[e] = mb.slot[i];
+        B.mv_old[e] = mb.oldb[i];
+        B.mv_new[e] = mb.newb[i];
+      } else {
+        ++drop;
+      }
+    }
+    if (drop) atomicAdd(&B.ctr[CTR_NDROP], drop);
+  }
+  mb.cnt = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Every lane of the wave must call it (uniform control flow).
+__device__ __forceinline__ void mb_append(MoverBuf& mb, const KBins& B, bool pred, int slot,
+                                          int ob, int nb) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return;
+  const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+  if (pred) {
+    mb.slot[mb.cnt + rank] = slot;
+    mb.oldb[mb.cnt + rank] = ob;
+    mb.newb[mb.cnt + rank] = nb;
+  }
+  mb.cnt += (int)__popcll(m);
+  if (mb.cnt > MBUF - PIC_WAVE) mb_flush(mb, B);
+}
+
 // Bytes of LDS in front of the window: bin offsets (nb + 1) and lengths (nb).
 __host__ __device__ __forceinline__ size_t tile_smem_head(const KBins& kb) {
   size_t nb = (size_t)kb.T[0] * kb.T[1] * kb.T[2];
