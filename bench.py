@@ -34,8 +34,11 @@ def parse():
     ap.add_argument("--path", default="auto")
     ap.add_argument("--n", type=int, default=128, help="cells per dimension")
     ap.add_argument("--ppc", type=int, default=8)
+    ap.add_argument("--tile", default="8x8x4", help="particle tile, cells (x by y by z)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="end with one plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -59,7 +62,8 @@ def main():
     grid = pic.Grid(params)
     nslots = pic.slots_for(N, ncell, slack)
     parts = pic.Particles.from_arrays(arrays, nslots)
-    bins = pic.Bins(grid, (8, 8, 8), slack, nslots)
+    tile = tuple(int(t) for t in args.tile.split("x"))
+    bins = pic.Bins(grid, tile, slack, nslots)
     pic.rebin(grid, parts, bins, pic.REBIN_FULL)
     J = pic.new_J(grid)
     path = pic.PATH_NAMES[args.path]
@@ -120,7 +124,7 @@ def main():
         "config": {"workload": f"uniform plasma {args.n}^3 cells, {args.ppc} per cell, order 3, "
                                f"periodic, u~N(0,0.05), dt 0.2; step = deposit (fused drift + "
                                f"mover detection) + incremental rebin",
-                   "particles": int(N), "cells": ncell, "path": args.path, "tile": [8, 8, 8],
+                   "particles": int(N), "cells": ncell, "path": args.path, "tile": list(tile),
                    "slack": slack},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -136,6 +140,13 @@ def main():
         out["paths"] = path_table(pic, torch, grid, parts, bins, N, ncell)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     bins.close()
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out), flush=True)
 
 

@@ -1,23 +1,25 @@
 // Per-cell deposition on VALU: the rhocell of Sec. 3.4 (Eq. 4) / Sec. 4.2.1 kept in
 // registers.
 //
-// A workgroup owns one particle tile and has three waves, one per current component. It
-// walks the tile in groups of 64 consecutive cells (one z-plane of an 8 x 8 x T tile).
-// Bins are contiguous, so a group's particles are one contiguous slot range.
-//  stage      all waves, lanes = slots, coalesced loads: position -> cell + float32 offset
-//             (FP64 only here) and amplitude q W v_c; the fused drift and mover detection
-//             (stage 1 of Alg. 2) also run here, once per particle, movers going to a
-//             per-wave LDS buffer. Offsets and amplitudes go to LDS in cell order with
-//             the gap slots skipped. A particle whose cell no longer matches its bin is
-//             deposited at once through the per-particle path.
-//  accumulate lanes = cells: the lane of wave c walks its cell's staged particles and
-//             accumulates (amp_c s_x) (x) s_y (x) s_z of component c on the cell's padded
-//             stencil window in registers (Eq. 4).
-//  flush      once per cell and component, into the tile window in LDS (Eq. 5) with plain
-//             read-add-write. The waves write different components, so they never share
-//             a word. LDS float atomics cost about 190 cycles per wave instruction on
-//             gfx950 (integer ones about 5) and are not used. The tile window then goes to
-//             the window scratch; k_halo_sum adds neighbouring tiles into J.
+// A workgroup owns one particle tile and walks it in groups of 64 consecutive cells (one
+// z-plane of an 8 x 8 x T tile). Bins are contiguous, so a group's particles are one
+// contiguous slot range; a unit is up to CV_CAP particles of one group. Four waves:
+//  producer   (wave 3) stages unit u + 1 while the consumers work on unit u. Lanes = slots,
+//             coalesced loads: position -> cell + float32 offset (FP64 only here) and
+//             amplitude q W v_c; the fused drift and mover detection (stage 1 of Alg. 2)
+//             also run here, once per particle, movers going to an LDS buffer. Offsets and
+//             amplitudes go to a double-buffered LDS stage in cell order, gap slots
+//             skipped. A particle whose cell no longer matches its bin goes to a stale list.
+//  consumers  (wave c = 0, 1, 2: component c) lanes = cells: each lane walks its cell's
+//             staged particles and accumulates (amp_c s_x) (x) s_y (x) s_z of component c
+//             on the cell's padded stencil window in registers (Eq. 4); after the group's
+//             last unit it adds them to the tile window in LDS (Eq. 5) with plain
+//             read-add-write. The consumers write different components, so they never
+//             share a word. LDS float atomics cost about 190 cycles per wave instruction
+//             on gfx950 (integer ones about 5) and are not used.
+//  end        the consumers add the stale particles (one at a time, lanes = stencil nodes)
+//             and the tile window goes to the window scratch; k_halo_sum adds neighbouring
+//             tiles into J.
 // Staggered axes use a window one node wider than the stencil (the stencil of a particle
 // in cell i starts at i + lo or i + lo + 1 depending on which half of the cell it is in);
 // the extra node carries a zero weight.
@@ -49,125 +51,253 @@ __device__ __forceinline__ int wave_max(int v) {
 }
 
 constexpr int CV_GROUP = 64;    // cells per group (lanes)
-constexpr int CV_CAP = 512;     // staged particles per round (gaps skipped)
+constexpr int CV_CAP = 512;     // staged particles per unit (gap slots skipped)
 constexpr int CV_MAPW = 1024;   // slots covered by one slot -> cell map window
-constexpr int CV_WAVES = 3;     // one wave per current component
+constexpr int CV_CONS = 3;      // consumer waves, one per current component
+constexpr int CV_PROD = 1;      // producer waves
+constexpr int CV_WAVES = CV_CONS + CV_PROD;
+constexpr int CV_STALE = 128;   // stale particles a tile keeps for the end phase
+
+// A particle found in the bin of another cell, kept for the end phase.
+struct StaleRec {
+  int cell[3];
+  float f[3];
+  float amp[3];
+};
 
 // LDS layout of one workgroup (bytes): bin offsets and lengths | tile window (3 comps)
-// | staged offsets f[3][CAP] and amplitudes a[3][CAP] | slot -> cell map | mover buffers.
+// | two stage buffers f[3][CAP], a[3][CAP] | per producer: slot -> cell map and mover
+// buffer | stale list and its count.
 template <int O, int DIM>
 struct CellLayout {
-  size_t win_off, stage_off, map_off, mb_off, total;
+  size_t win_off, stage_off, map_off, mb_off, stale_off, total;
   __host__ __device__ explicit CellLayout(const KBins& kb) {
     win_off = tile_smem_head(kb);
     stage_off = win_off + (((size_t)3 * TileWin<O, DIM>::max_size(kb) * sizeof(float) + 15) & ~(size_t)15);
-    map_off = stage_off + (size_t)6 * CV_CAP * sizeof(float);
-    mb_off = map_off + CV_MAPW;
-    total = mb_off + (size_t)CV_WAVES * 3 * MBUF * sizeof(int32_t);
+    map_off = stage_off + (size_t)2 * 6 * CV_CAP * sizeof(float);
+    mb_off = map_off + (size_t)CV_PROD * CV_MAPW;
+    stale_off = mb_off + (size_t)CV_PROD * 3 * MBUF * sizeof(int32_t);
+    total = stale_off + (size_t)CV_STALE * sizeof(StaleRec) + 16;
   }
 };
 
+// A unit of work: up to CV_CAP particles of one group of 64 consecutive cells. Every
+// wave walks the same sequence of units (empty groups skipped).
 struct CellGroup {
   int g0, gn;        // first tile-local bin, cells
   int S0, S1;        // slot range
   int n, st;         // this lane's cell: particles (valid slots), staged offset
   int ntot;          // particles of the group
+  int R0;            // staged index of the unit's first particle
 };
 
-// Stage the group's particles with staged index in [R0, R0 + CV_CAP): the three waves
-// share the slot chunks, lanes = slots (coalesced loads).
+// The group starting at tile-local bin g0 (g0 >= nb: past the end, no particles). Every
+// field is written once, so the struct stays in registers.
+__device__ __forceinline__ CellGroup cv_group_at(int g0, const int32_t* s_off,
+                                                 const int32_t* s_len, int nb, int lane) {
+  const bool valid = g0 < nb;
+  const int gs = valid ? g0 : 0;
+  const int gn = valid ? min(CV_GROUP, nb - g0) : 0;
+  const int n = lane < gn ? s_len[gs + lane] : 0;
+  int incl = n;
+#pragma unroll
+  for (int off = 1; off < PIC_WAVE; off <<= 1) {
+    const int t = __shfl_up(incl, off);
+    if (lane >= off) incl += t;
+  }
+  CellGroup gr;
+  gr.g0 = g0;
+  gr.gn = gn;
+  gr.S0 = valid ? s_off[gs] : 0;
+  gr.S1 = valid ? s_off[gs + gn] : 0;
+  gr.n = n;
+  gr.st = incl - n;
+  gr.ntot = __shfl(incl, PIC_WAVE - 1);
+  gr.R0 = 0;
+  return gr;
+}
+
+__device__ __forceinline__ CellGroup cv_first_unit(int g0, const int32_t* s_off,
+                                                   const int32_t* s_len, int nb, int lane) {
+  CellGroup gr = cv_group_at(g0, s_off, s_len, nb, lane);
+  while (gr.g0 < nb && gr.ntot == 0) gr = cv_group_at(gr.g0 + CV_GROUP, s_off, s_len, nb, lane);
+  return gr;
+}
+
+__device__ __forceinline__ CellGroup cv_next_unit(const CellGroup& cur, const int32_t* s_off,
+                                                  const int32_t* s_len, int nb, int lane) {
+  if (cur.R0 + CV_CAP < cur.ntot) {
+    CellGroup gr = cur;
+    gr.R0 = cur.R0 + CV_CAP;
+    return gr;
+  }
+  return cv_first_unit(cur.g0 + CV_GROUP, s_off, s_len, nb, lane);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Raw particle data of one slot, fetched one chunk ahead of its use.
+struct CvRaw {
+  double x, y, z;
+  float ux, uy, uz, w;
+  int s, lc, si;
+};
+
+// w[i] by selects (the empty asm keeps the compiler from turning it into an indexed
+// load from a stack copy of w).
+template <int O>
+__device__ __forceinline__ float pick_w(const float* w, int i) {
+  float v = w[0];
+#pragma unroll
+  for (int k = 1; k <= O; ++k) {
+    float wk = w[k];
+    asm volatile("" : "+v"(wk));
+    v = i == k ? wk : v;
+  }
+  return v;
+}
+
+// One particle through global atomics (the rare overflow of a tile's stale list).
+template <int O, int DIM>
+__device__ __forceinline__ void cv_particle_global(const KGrid& G, PartPrep<O, DIM> p,
+                                                float* const* J, uint32_t& bad) {
+  prep_shapes(p);
+  scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
+    int ix = store_idx(G, 0, mx), iy = store_idx(G, 1, my);
+    int iz = DIM == 3 ? store_idx(G, 2, mz) : 0;
+    if ((ix | iy | iz) < 0) {
+      if (v != 0.0f) bad |= PIC_EF_STENCIL;
+      return;
+    }
+    unsafeAtomicAdd(&J[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
+  });
+}
+
+// Producer wave: stage the unit's particles (staged index in [R0, R0 + CV_CAP)) into one
+// stage buffer, lanes = slots (coalesced loads, the next chunk's loads in flight while the
+// current chunk is processed).
 template <int O, int DIM>
 __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const KPart& P,
                                          const TileBox& tb, const int32_t* s_off,
-                                         const int32_t* s_len, const CellGroup& gr, int R0,
-                                         float* sf, float* sa, int8_t* map, MoverBuf& mb,
-                                         float* const* J, unsigned flags, double dt,
-                                         uint32_t& bad) {
-  const int wave = threadIdx.x / PIC_WAVE;
+                                         const int32_t* s_len, const CellGroup& gr, float* sf,
+                                         float* sa, int8_t* map, MoverBuf& mb, StaleRec* stale,
+                                         int* s_nstale, float* const* J, unsigned flags,
+                                         double dt, uint32_t& bad) {
   const int lane = threadIdx.x % PIC_WAVE;
+  const int pw = threadIdx.x / PIC_WAVE - CV_CONS;   // producer index
   const bool emit = flags & PIC_F_EMIT_MOVERS;
   const bool drift = flags & PIC_F_DRIFT;
   const int ex = tb.e[0], exy = tb.e[0] * tb.e[1];
   for (int lo = gr.S0; lo < gr.S1; lo += CV_MAPW) {
     const int hi = min(gr.S1, lo + CV_MAPW);
-    __syncthreads();
-    for (int i = threadIdx.x; i < hi - lo; i += blockDim.x) map[i] = -1;
-    __syncthreads();
-    if (wave == 0 && lane < gr.gn) {
+    wave_lds_sync();
+    for (int i = lane; i < hi - lo; i += PIC_WAVE) map[i] = -1;
+    wave_lds_sync();
+    if (lane < gr.gn) {
       const int c = gr.g0 + lane;
       const int a = max(s_off[c], lo), b = min(s_off[c] + s_len[c], hi);
       for (int q = a; q < b; ++q) map[q - lo] = (int8_t)lane;
     }
-    __syncthreads();
-    for (int base = lo + wave * PIC_WAVE; base < hi; base += CV_WAVES * PIC_WAVE) {
-      const int s = base + lane;
-      int lc = s < hi ? (int)map[s - lo] : -1;
-      const int lcs = lc < 0 ? 0 : lc;
-      const int si = __shfl(gr.st, lcs) + (s - s_off[gr.g0 + lcs]) - R0;
-      if (si < 0 || si >= CV_CAP) lc = -1;          // staged in another round
-      const int lb = gr.g0 + lcs;
+    wave_lds_sync();
+    const int first = lo + pw * PIC_WAVE, step = CV_PROD * PIC_WAVE;
+    auto fetch = [&](int base, CvRaw& r) {
+      r.s = base + lane;
+      r.lc = r.s < hi ? (int)map[r.s - lo] : -1;
+      const int lcs = r.lc < 0 ? 0 : r.lc;
+      r.si = __shfl(gr.st, lcs) + (r.s - s_off[gr.g0 + lcs]) - gr.R0;
+      if (r.si < 0 || r.si >= CV_CAP) r.lc = -1;   // staged in another unit
+      if (r.lc >= 0) {
+        r.x = P.x[r.s];
+        r.y = P.y[r.s];
+        r.z = DIM == 3 ? P.z[r.s] : 0.0;
+        r.ux = P.ux[r.s];
+        r.uy = P.uy[r.s];
+        r.uz = P.uz[r.s];
+        r.w = P.w[r.s];
+      }
+    };
+    CvRaw nxt;
+    if (first < hi) fetch(first, nxt);
+    for (int base = first; base < hi; base += step) {
+      const CvRaw r = nxt;
+      if (base + step < hi) fetch(base + step, nxt);
+      const int lb = gr.g0 + (r.lc < 0 ? 0 : r.lc);
       PartPrep<O, DIM> p;
-      double pos[3] = {0.0, 0.0, 0.0};
-      float ux = 0.f, uy = 0.f, uz = 0.f;
+      double pos[3] = {r.x, r.y, r.z};
       bool ok = false, mine = false;
-      if (lc >= 0) {
-        pos[0] = P.x[s];
-        pos[1] = P.y[s];
-        if (DIM == 3) pos[2] = P.z[s];
-        ux = P.ux[s];
-        uy = P.uy[s];
-        uz = P.uz[s];
-        const float w = P.w[s];
+      if (r.lc >= 0) {
         ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad);
-        if (ok) {
-          prep_amp(G.q, ux, uy, uz, w, p.amp);
-          const int cz = lb / exy, cy = (lb - cz * exy) / ex, cxx = lb - cz * exy - cy * ex;
-          mine = p.cell[0] == tb.c0[0] + cxx && p.cell[1] == tb.c0[1] + cy &&
-                 (DIM == 2 || p.cell[2] == tb.c0[2] + cz);
+        prep_amp(G.q, r.ux, r.uy, r.uz, r.w, p.amp);
+        // the particle's cell relative to the tile -> local bin (no division)
+        const int lx = p.cell[0] - tb.c0[0], ly = p.cell[1] - tb.c0[1];
+        const int lz = DIM == 3 ? p.cell[2] - tb.c0[2] : 0;
+        const bool in = (unsigned)lx < (unsigned)tb.e[0] && (unsigned)ly < (unsigned)tb.e[1] &&
+                        (unsigned)lz < (unsigned)(DIM == 3 ? tb.e[2] : 1);
+        mine = ok && in && lx + ex * (ly + tb.e[1] * lz) == lb;
+      }
+      // stale particle (its cell no longer matches its bin): kept for the end phase, or,
+      // when the tile's list is full, deposited at once through global atomics
+      const bool st = ok && !mine;
+      const unsigned long long m = __ballot(st);
+      if (m) {
+        int e0 = 0;
+        if (lane == 0) e0 = atomicAdd(s_nstale, (int)__popcll(m));
+        e0 = __shfl(e0, 0);
+        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (st) {
+          if (e0 + rank < CV_STALE) {
+            StaleRec& q = stale[e0 + rank];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              q.cell[d] = d < DIM ? p.cell[d] : 0;
+              q.f[d] = d < DIM ? p.f[d] : 0.0f;
+              q.amp[d] = p.amp[d];
+            }
+          } else {
+            cv_particle_global<O, DIM>(G, p, J, bad);
+          }
         }
       }
-      if (ok && !mine) {
-        // stale particle (cell no longer matches its bin): exact per-particle path
-        prep_shapes(p);
-        scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
-          int ix = store_idx(G, 0, mx), iy = store_idx(G, 1, my);
-          int iz = DIM == 3 ? store_idx(G, 2, mz) : 0;
-          if ((ix | iy | iz) < 0) {
-            if (v != 0.0f) bad |= PIC_EF_STENCIL;
-            return;
-          }
-          unsafeAtomicAdd(&J[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
-        });
-      }
-      if (lc >= 0) {
+      if (r.lc >= 0) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          sf[d * CV_CAP + si] = mine ? p.f[d] : 0.0f;
-          sa[d * CV_CAP + si] = mine ? p.amp[d] : 0.0f;
+          sf[d * CV_CAP + r.si] = mine ? p.f[d] : 0.0f;
+          sa[d * CV_CAP + r.si] = mine ? p.amp[d] : 0.0f;
         }
       }
       if (ok && drift) {
+        float ux = r.ux, uy = r.uy, uz = r.uz;
         drift_one<DIM>(G, pos, ux, uy, uz, dt);
-        P.x[s] = pos[0];
-        P.y[s] = pos[1];
-        if (DIM == 3) P.z[s] = pos[2];
+        P.x[r.s] = pos[0];
+        P.y[r.s] = pos[1];
+        if (DIM == 3) P.z[r.s] = pos[2];
       }
       if (emit) {
+        // mover: its (new) cell differs from the cell of the bin it sits in
         bool mv = false;
         int32_t nbn = -1;
         if (ok) {
           int c2[3];
           float f2[3];
           if (prep_cell<DIM>(G, pos[0], pos[1], pos[2], c2, f2, bad)) {
-            nbn = bin_of_cell(G.n, B.T, c2[0], c2[1], c2[2]);
-            mv = nbn != tb.b0 + lb;
+            const int lx = c2[0] - tb.c0[0], ly = c2[1] - tb.c0[1];
+            const int lz = DIM == 3 ? c2[2] - tb.c0[2] : 0;
+            const bool in = (unsigned)lx < (unsigned)tb.e[0] && (unsigned)ly < (unsigned)tb.e[1] &&
+                            (unsigned)lz < (unsigned)(DIM == 3 ? tb.e[2] : 1);
+            const int loc = lx + ex * (ly + tb.e[1] * lz);
+            mv = !(in && loc == lb);
+            if (mv) nbn = in ? tb.b0 + loc : bin_of_cell(G.n, B.T, c2[0], c2[1], c2[2]);
           }
         }
-        mb_append(mb, B, mv, s, tb.b0 + lb, nbn);
+        mb_append(mb, B, mv, r.s, tb.b0 + lb, nbn);
       }
     }
   }
-  __syncthreads();
 }
 
 // Accumulate component C of the lane's cell from the staged particles [k0, k1).
@@ -259,56 +389,94 @@ __host__ __device__ constexpr int csz_max() {
                                          : (csz<O, DIM>(1) > csz<O, DIM>(2) ? csz<O, DIM>(1) : csz<O, DIM>(2));
 }
 
-// One group: rounds of staging (all waves) and accumulation (wave c: component c), then
-// the flush. The branches on the wave index are uniform within each wave and hold no
-// barrier; every wave runs the same rounds, so all reach the same barriers.
-template <int O, int DIM>
-__device__ __forceinline__ void cv_group(const KGrid& G, const KBins& B, const KPart& P,
-                                         const TileBox& tb, const TileWin<O, DIM>& tw,
-                                         const int32_t* s_off, const int32_t* s_len,
-                                         const CellGroup& gr, float* sf, float* sa, int8_t* map,
-                                         MoverBuf& mb, float* win, float* const* J,
-                                         unsigned flags, double dt, uint32_t& bad) {
-  constexpr int NA = csz_max<O, DIM>();
-  const int wave = threadIdx.x / PIC_WAVE;
+
+// End phase, wave C: component C of every stale particle of the tile, one particle at a
+// time with lanes = stencil nodes (distinct nodes, so plain read-add-write into the tile
+// window; nodes outside the window go to J with global atomics).
+template <int O, int DIM, int C>
+__device__ __forceinline__ void cv_stale(const KGrid& G, const TileWin<O, DIM>& tw,
+                                         const StaleRec* stale, int nstale, float* win,
+                                         float* const* J, uint32_t& bad) {
+  constexpr int NS = (O + 1) * (O + 1) * (DIM == 3 ? O + 1 : 1);
   const int lane = threadIdx.x % PIC_WAVE;
-  const bool own = lane < gr.gn;
-  float acc[NA];
+  for (int e = 0; e < nstale; ++e) {
+    const StaleRec q = stale[e];
+    float w[3][O + 1];
+    int base[3] = {0, 0, 0};
 #pragma unroll
-  for (int i = 0; i < NA; ++i) acc[i] = 0.0f;
-  for (int R0 = 0; R0 < gr.ntot; R0 += CV_CAP) {
-    cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, gr, R0, sf, sa, map, mb, J, flags, dt, bad);
-    const int k0 = min(max(gr.st, R0), R0 + CV_CAP) - R0;
-    const int k1 = min(max(gr.st + gr.n, R0), R0 + CV_CAP) - R0;
-    if (wave == 0) cv_accumulate<O, DIM, 0>(k0, k1, sf, sa, acc);
-    else if (wave == 1) cv_accumulate<O, DIM, 1>(k0, k1, sf, sa, acc);
-    else cv_accumulate<O, DIM, 2>(k0, k1, sf, sa, acc);
-  }
-  if (gr.ntot > 0) {
-    const int ex = tb.e[0], exy = tb.e[0] * tb.e[1];
-    const int cell = gr.g0 + (own ? lane : 0);
-    int cc[3];
-    cc[2] = cell / exy;
-    cc[1] = (cell - cc[2] * exy) / ex;
-    cc[0] = cell - cc[2] * exy - cc[1] * ex;
+    for (int d = 0; d < DIM; ++d) {
+      int sh;
+      if (d == C) sh = shape_w<O, true>(q.f[d], w[d]);
+      else sh = shape_w<O, false>(q.f[d], w[d]);
+      base[d] = q.cell[d] + win_lo(O, d == C) + sh;
+    }
+    for (int j = lane; j < NS; j += PIC_WAVE) {
+      const int ix = j % (O + 1), iy = (j / (O + 1)) % (O + 1), iz = j / ((O + 1) * (O + 1));
+      float v = q.amp[C] * pick_w<O>(w[0], ix) * pick_w<O>(w[1], iy);
+      if (DIM == 3) v *= pick_w<O>(w[2], iz);
+      const int m[3] = {base[0] + ix, base[1] + iy, DIM == 3 ? base[2] + iz : 0};
+      bool in = true;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) cc[d] += tb.c0[d];
-    const bool plane = DIM == 3 && (gr.g0 / exy) == ((gr.g0 + gr.gn - 1) / exy);
-    const bool o = own && gr.n > 0;
-#define CV_FLUSH(C_)                                                     \
-  if (plane) cv_flush<O, DIM, C_, true>(tw, cc, acc, win, o);            \
-  else cv_flush<O, DIM, C_, false>(tw, cc, acc, win, o)
-    if (wave == 0) { CV_FLUSH(0); }
-    else if (wave == 1) { CV_FLUSH(1); }
-    else { CV_FLUSH(2); }
-#undef CV_FLUSH
+      for (int d = 0; d < DIM; ++d) in = in && m[d] >= tw.o[d] && m[d] < tw.o[d] + tw.W[d];
+      if (in) {
+        const int a = tw.index(C, m[0], m[1], m[2]);
+        win[a] = win[a] + v;
+      } else {
+        const int sx = store_idx(G, 0, m[0]), sy = store_idx(G, 1, m[1]);
+        const int sz = DIM == 3 ? store_idx(G, 2, m[2]) : 0;
+        if ((sx | sy | sz) < 0) {
+          if (v != 0.0f) bad |= PIC_EF_STENCIL;
+        } else {
+          unsafeAtomicAdd(&J[C][((int64_t)sz * G.N[1] + sy) * G.N[0] + sx], v);
+        }
+      }
+    }
+    asm volatile("" ::: "memory");
   }
 }
 
+// Consumer wave C: flush component C of the group's cells into the tile window.
+template <int O, int DIM, int C>
+__device__ __forceinline__ void cv_flush_group(const TileBox& tb, const TileWin<O, DIM>& tw,
+                                               const CellGroup& gr, const float* acc,
+                                               float* win) {
+  const int lane = threadIdx.x % PIC_WAVE;
+  const bool own = lane < gr.gn;
+  const int ex = tb.e[0], exy = tb.e[0] * tb.e[1];
+  const int cell = gr.g0 + (own ? lane : 0);
+  int cc[3];
+  cc[2] = cell / exy;
+  cc[1] = (cell - cc[2] * exy) / ex;
+  cc[0] = cell - cc[2] * exy - cc[1] * ex;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) cc[d] += tb.c0[d];
+  const bool plane = DIM == 3 && (gr.g0 / exy) == ((gr.g0 + gr.gn - 1) / exy);
+  const bool o = own && gr.n > 0;
+  if (plane) cv_flush<O, DIM, C, true>(tw, cc, acc, win, o);
+  else cv_flush<O, DIM, C, false>(tw, cc, acc, win, o);
+}
+
+template <int O, int DIM, int C>
+__device__ __forceinline__ void cv_consume(int k0, int k1, const float* sf, const float* sa,
+                                           float* acc, bool last, const TileBox& tb,
+                                           const TileWin<O, DIM>& tw, const CellGroup& gr,
+                                           float* win) {
+  cv_accumulate<O, DIM, C>(k0, k1, sf, sa, acc);
+  if (last) {
+    cv_flush_group<O, DIM, C>(tb, tw, gr, acc, win);
+#pragma unroll
+    for (int i = 0; i < csz_max<O, DIM>(); ++i) acc[i] = 0.0f;
+  }
+}
+
+// One workgroup per tile: the producer wave(s) stage unit u + 1 while waves 0..2 accumulate
+// unit u. Every wave walks the same units and passes the same number of barriers. (A
+// workgroup of more than four waves was measured to fit only once per CU.)
 template <int O, int DIM>
-__global__ __launch_bounds__(CV_WAVES * PIC_WAVE) void k_dep_cell_valu(
+__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 4) void k_dep_cell_valu(
     KGrid G, KBins B, KPart P, float* __restrict__ J0, float* __restrict__ J1,
     float* __restrict__ J2, unsigned flags, double dt) {
+  constexpr int NA = csz_max<O, DIM>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const CellLayout<O, DIM> L(B);
   const TileBox tb = tile_box(G.n, B.T, B.nt, blockIdx.x);
@@ -316,38 +484,72 @@ __global__ __launch_bounds__(CV_WAVES * PIC_WAVE) void k_dep_cell_valu(
   int32_t* s_off = (int32_t*)smem_raw;
   int32_t* s_len = s_off + tb.nb + 1;
   float* win = (float*)(smem_raw + L.win_off);
-  float* sf = (float*)(smem_raw + L.stage_off);
-  float* sa = sf + 3 * CV_CAP;
-  int8_t* map = (int8_t*)(smem_raw + L.map_off);
-  float* J[3] = {J0, J1, J2};
+  float* stage = (float*)(smem_raw + L.stage_off);
   const int wave = threadIdx.x / PIC_WAVE;
   const int lane = threadIdx.x % PIC_WAVE;
-  int32_t* mbb = (int32_t*)(smem_raw + L.mb_off) + wave * 3 * MBUF;
+  const bool producer = wave >= CV_CONS;
+  const int pw = producer ? wave - CV_CONS : 0;
+  int8_t* map_p = (int8_t*)(smem_raw + L.map_off) + pw * CV_MAPW;
+  int32_t* mbb = (int32_t*)(smem_raw + L.mb_off) + pw * 3 * MBUF;
+  StaleRec* stale = (StaleRec*)(smem_raw + L.stale_off);
+  int* s_nstale = (int*)(smem_raw + L.stale_off + CV_STALE * sizeof(StaleRec));
+  float* J[3] = {J0, J1, J2};
   MoverBuf mb{mbb, mbb + MBUF, mbb + 2 * MBUF, 0};
   for (int i = threadIdx.x; i <= tb.nb; i += blockDim.x) s_off[i] = B.off[tb.b0 + i];
   for (int i = threadIdx.x; i < tb.nb; i += blockDim.x) s_len[i] = B.len[tb.b0 + i];
   for (int i = threadIdx.x; i < 3 * tw.size; i += blockDim.x) win[i] = 0.0f;
+  if (threadIdx.x == 0) *s_nstale = 0;
   __syncthreads();
   uint32_t bad = 0;
-  for (int g0 = 0; g0 < tb.nb; g0 += CV_GROUP) {
-    CellGroup gr;
-    gr.g0 = g0;
-    gr.gn = min(CV_GROUP, tb.nb - g0);
-    gr.S0 = s_off[g0];
-    gr.S1 = s_off[g0 + gr.gn];
-    gr.n = lane < gr.gn ? s_len[g0 + lane] : 0;
-    // exclusive scan of the cells' particle counts -> staged offsets
-    int incl = gr.n;
-#pragma unroll
-    for (int off = 1; off < PIC_WAVE; off <<= 1) {
-      const int t = __shfl_up(incl, off);
-      if (lane >= off) incl += t;
+  CellGroup cur = cv_first_unit(0, s_off, s_len, tb.nb, lane);
+  // The producer and the consumers run separate loops over the same units with one
+  // barrier per unit (plus one after the first unit is staged), so the consumers'
+  // accumulators are not live across the producer's code.
+  if (producer) {
+    if (cur.g0 < tb.nb)
+      cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, map_p, mb, stale,
+                       s_nstale, J, flags, dt, bad);
+    __syncthreads();
+    int ub = 0;
+    while (cur.g0 < tb.nb) {
+      const CellGroup nxt = cv_next_unit(cur, s_off, s_len, tb.nb, lane);
+      if (nxt.g0 < tb.nb) {
+        float* nf = stage + (ub ^ 1) * 6 * CV_CAP;
+        cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, map_p, mb, stale,
+                         s_nstale, J, flags, dt, bad);
+      }
+      __syncthreads();
+      cur = nxt;
+      ub ^= 1;
     }
-    gr.st = incl - gr.n;
-    gr.ntot = __shfl(incl, PIC_WAVE - 1);
-    cv_group<O, DIM>(G, B, P, tb, tw, s_off, s_len, gr, sf, sa, map, mb, win, J, flags, dt, bad);
+    if (flags & PIC_F_EMIT_MOVERS) mb_flush(mb, B);
+  } else {
+    float acc[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acc[i] = 0.0f;
+    __syncthreads();
+    int ub = 0;
+    while (cur.g0 < tb.nb) {
+      const CellGroup nxt = cv_next_unit(cur, s_off, s_len, tb.nb, lane);
+      const float* sf = stage + ub * 6 * CV_CAP;
+      const int k0 = min(max(cur.st, cur.R0), cur.R0 + CV_CAP) - cur.R0;
+      const int k1 = min(max(cur.st + cur.n, cur.R0), cur.R0 + CV_CAP) - cur.R0;
+      const bool last = cur.R0 + CV_CAP >= cur.ntot;
+      if (wave == 0) cv_consume<O, DIM, 0>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
+      else if (wave == 1) cv_consume<O, DIM, 1>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
+      else cv_consume<O, DIM, 2>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
+      __syncthreads();
+      cur = nxt;
+      ub ^= 1;
+    }
   }
-  if (flags & PIC_F_EMIT_MOVERS) mb_flush(mb, B);
+  __syncthreads();
+  const int ns = min(*s_nstale, CV_STALE);
+  if (ns > 0) {
+    if (wave == 0) cv_stale<O, DIM, 0>(G, tw, stale, ns, win, J, bad);
+    else if (wave == 1) cv_stale<O, DIM, 1>(G, tw, stale, ns, win, J, bad);
+    else if (wave == 2) cv_stale<O, DIM, 2>(G, tw, stale, ns, win, J, bad);
+  }
   if (bad) atomicOr(B.err, bad);
   __syncthreads();
   store_window(B, blockIdx.x, tw, win, blockDim.x, threadIdx.x);

@@ -90,9 +90,9 @@ struct SubWin {
 };
 
 // Per-wave mover buffer in LDS: movers are appended with a ballot and a lane prefix
-// count (no global atomic per chunk) and copied to the global list, one atomic per
-// flush, when it fills and at the end of the tile.
-constexpr int MBUF = 128;
+// count and copied to the global list, with one global atomic per flush, when it fills
+// and at the end of the tile (usually once per tile: the list counter is contended).
+constexpr int MBUF = 256;
 
 struct MoverBuf {
   int32_t* slot;

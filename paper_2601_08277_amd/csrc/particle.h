@@ -113,8 +113,12 @@ __device__ __forceinline__ void drift_one(const KGrid& G, double* pos, float ux,
     double xn = pos[d] + v * dt;
     if (G.per[d]) {
       double t = xn - G.x0[d];
-      const double fl = floor(t / G.L[d]);
-      t = t - G.L[d] * fl;
+      // t - L floor(t / L); for 0 <= t < L the quotient is below 1, floor gives 0 and t
+      // is unchanged, so only the particles that leave the box divide
+      if (!(t >= 0.0 && t < G.L[d])) {
+        const double fl = floor(t / G.L[d]);
+        t = t - G.L[d] * fl;
+      }
       xn = t + G.x0[d];
     }
     pos[d] = xn;

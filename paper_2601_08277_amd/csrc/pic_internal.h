@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/pic.h"
+#include "pic.h"
 
 #define PIC_MAX_ORDER 3
 #define PIC_WAVE 64
@@ -79,19 +79,14 @@ struct KBins {
 __device__ __forceinline__ int to_cell(double x, double x0, double inv, int n, float& f,
                                        uint32_t& bad) {
 #pragma clang fp contract(off)
-  double xi = (x - x0) * inv;
-  if (!(xi == xi) || __builtin_isinf(xi)) {
-    bad |= PIC_EF_NONFINITE;
-    return -1;
-  }
+  const double xi = (x - x0) * inv;
   double fl = floor(xi);
-  if (xi == (double)n) fl = (double)(n - 1);
-  if (!(fl >= 0.0 && fl < (double)n)) {
-    bad |= PIC_EF_DOMAIN;
-    return -1;
-  }
+  fl = xi == (double)n ? (double)(n - 1) : fl;
+  const bool fin = __builtin_isfinite(xi);
+  const bool in = fl >= 0.0 && fl < (double)n;   // false for NaN
+  bad |= !fin ? (uint32_t)PIC_EF_NONFINITE : (!in ? (uint32_t)PIC_EF_DOMAIN : 0u);
   f = (float)(xi - fl);
-  return (int)fl;
+  return (fin && in) ? (int)(in ? fl : 0.0) : -1;
 }
 
 // ---------------------------------------------------------------------------------
