@@ -24,6 +24,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "deposit_cell_valu_c2_128cubed_o3_hbm_counters.md")
+
+
+def measured_traffic(path, tile, n, ppc):
+    """HBM bytes per deposition call from the committed rocprofv3 counter summary, or None
+    when the summary does not match this workload or the deposition sources changed since
+    the counters were taken."""
+    import hashlib
+    if path not in ("auto", "cell_valu") or tile != (8, 8, 4) or n != 128 or ppc != 8:
+        return None
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    kv = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_", "source_")))
+    h = hashlib.sha256()
+    for f in kv.get("source_files", "").split():
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != kv.get("source_sha256"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -127,8 +151,10 @@ def main():
                    "particles": int(N), "cells": ncell, "path": args.path, "tile": list(tile),
                    "slack": slack},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "deposition (fused drift + mover detection)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.path, tile, args.n, args.ppc),
+                     "kernel": "pic_deposit call = k_dep_cell_valu<3,3> + k_halo_sum<3,3> "
+                               "(fused drift + mover detection)",
                      "bytes_per_launch": dep_bytes, "kernel_ms": dep_ms},
         "breakdown_ms": {"deposit": dep_ms, "rebin": reb_ms,
                          "other": max(0.0, ms - dep_ms - reb_ms)},
