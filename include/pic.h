@@ -205,17 +205,35 @@ pic_status pic_deposit_backward(const pic_grid* grid, const pic_particles* p,
 pic_status pic_drift(const pic_grid* grid, pic_particles* p, double dt, hipStream_t stream);
 
 /* ---- batched patches ---------------------------------------------------------------
- * A plan holds `npatch` independent grids and their bins; one persistent kernel pulls
- * (patch, tile) work items from a device queue, mixing orders and densities. Tile shape
- * per patch comes from the autotuner cache `tune_cache_json` (host path to a JSON file,
- * nullable: built-in rule). Allocates device memory (synchronous). */
+ * Many independent 3D patches (uneven sizes, densities and shape orders) deposited by one
+ * persistent kernel that pulls (patch, tile) work items from a device counter, longest
+ * items first (the tile decomposition of Sec. 4.1, batched). `bins[k]` must have been made
+ * for `grids[k]` (its tile shape is the autotuner's choice, applied at pic_bins_create) and
+ * filled by pic_rebin(PIC_REBIN_FULL) before the first call. `tune_cache_json` is a host
+ * path to the autotuner's JSON cache or NULL; the plan reads its "blocks_per_cu" entry
+ * (persistent workgroups per compute unit, capped by occupancy; default: occupancy).
+ * pic_plan_create allocates device and pinned memory and synchronises; pic_plan_destroy
+ * synchronises the device and frees them. Errors: INVALID_ARG (bad grid, bins for another
+ * grid, unreadable cache), UNSUPPORTED (2D patch, tile window over the LDS limit). */
 pic_status pic_plan_create(const pic_grid* grids, int npatch, pic_bins* const* bins,
                            const char* tune_cache_json, pic_plan** out);
 pic_status pic_plan_destroy(pic_plan* plan);
-/* particles[k], J3[3k..3k+2] belong to patch k. No allocation, no host round trip:
- * safe to capture into a hipGraph. */
+/* Deposits every patch: particles[k] (host array of npatch descriptors; device SoA
+ * pointers) into J3[3k], J3[3k+1], J3[3k+2] (host array of 3 npatch device pointers), with
+ * the flags of pic_deposit (overwrite unless PIC_F_ACCUMULATE; PIC_F_DRIFT uses grids[k].dt;
+ * PIC_F_EMIT_MOVERS fills each patch's mover list for pic_rebin). path: PIC_PATH_AUTO or
+ * PIC_PATH_CELL_VALU (else UNSUPPORTED). Enqueues three kernels on `stream` and nothing
+ * else once the pointer set has been uploaded: the first call with new pointers copies the
+ * patch descriptors from pinned memory (and waits for the previous copy of that buffer),
+ * which is refused (INVALID_ARG) while `stream` is capturing. Calls with unchanged pointers
+ * allocate nothing, do not synchronise and contain no memset: safe to capture into a HIP
+ * graph. Calls that overlap on one plan race. */
 pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* particles,
                                float* const* J3, int path, unsigned flags, hipStream_t stream);
+/* Work items, persistent workgroups, workgroups per CU and LDS bytes per workgroup of a
+ * plan (any pointer may be NULL). */
+pic_status pic_plan_info(const pic_plan* plan, int* nitems, int* blocks, int* blocks_per_cu,
+                         int64_t* lds_bytes);
 
 /* Synchronises `stream` and reports the first device-side error recorded in `bins`
  * (PIC_OK if none); clears the flags. */

@@ -31,7 +31,7 @@ extern "C" const char* pic_last_error(void) { return g_last_error.c_str(); }
 // ----------------------------------------------------------------------------------
 static int min_guard(int order) { return order == 1 ? 1 : 2; }
 
-static pic_status validate_grid(const pic_grid* g) {
+pic_status validate_grid(const pic_grid* g) {
   if (!g) return set_error(PIC_ERR_INVALID_ARG, "grid is NULL");
   if (g->dim != 2 && g->dim != 3) return set_error(PIC_ERR_INVALID_ARG, "dim must be 2 or 3");
   if (g->order < 1 || g->order > 3)
@@ -57,7 +57,7 @@ static pic_status validate_grid(const pic_grid* g) {
   return PIC_OK;
 }
 
-static pic_status validate_particles(const pic_particles* p, int dim) {
+pic_status validate_particles(const pic_particles* p, int dim) {
   if (!p) return set_error(PIC_ERR_INVALID_ARG, "particles is NULL");
   if (p->nslots < 0 || p->nslots >= (1ll << 31) - 64)
     return set_error(PIC_ERR_INVALID_ARG, "nslots must be in [0, 2^31 - 64)");
@@ -67,7 +67,7 @@ static pic_status validate_particles(const pic_particles* p, int dim) {
   return PIC_OK;
 }
 
-static bool same_grid(const pic_grid& a, const pic_grid& b) {
+bool same_grid(const pic_grid& a, const pic_grid& b) {
   if (a.dim != b.dim) return false;
   for (int d = 0; d < 3; ++d)
     if (a.n[d] != b.n[d]) return false;

@@ -178,51 +178,102 @@ __global__ __launch_bounds__(256) void k_dep_tile_atomic(KGrid G, KBins B, KPart
 // J += sum of the stored tile windows covering each node (at most 2 tiles per
 // dimension for tiles at least as wide as the stencil reach). One thread per node, all
 // three components.
+// J node idx (flat, stored layout) = sum over the tile windows that cover it.
+template <int O, int DIM>
+__device__ __forceinline__ void halo_node(const KGrid& G, const KBins& B, float* __restrict__ J0,
+                                          float* __restrict__ J1, float* __restrict__ J2,
+                                          int64_t idx) {
+  constexpr int LO = TileWin<O, DIM>::LO, R = TileWin<O, DIM>::R;
+  const int n3[3] = {(int)(idx % G.N[0]), (int)((idx / G.N[0]) % G.N[1]),
+                     (int)(idx / ((int64_t)G.N[0] * G.N[1]))};
+  int tl[3][6], wl[3][6], cnt[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    cnt[d] = 0;
+    if (d >= DIM) {
+      tl[d][0] = 0;
+      wl[d][0] = 0;
+      cnt[d] = 1;
+      continue;
+    }
+    if (G.per[d]) {
+      for (int k = -1; k <= 1; ++k)
+        cnt[d] = halo_cands(n3[d] + k * G.n[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d],
+                            cnt[d]);
+    } else {
+      cnt[d] = halo_cands(n3[d] - G.g[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d], cnt[d]);
+    }
+  }
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  for (int a = 0; a < cnt[2]; ++a)
+    for (int b = 0; b < cnt[1]; ++b)
+      for (int c = 0; c < cnt[0]; ++c) {
+        const int t = tl[0][c] + B.nt[0] * (tl[1][b] + B.nt[1] * tl[2][a]);
+        const int W0 = min(B.T[0], G.n[0] - tl[0][c] * B.T[0]) + R;
+        const int W1 = DIM >= 2 ? min(B.T[1], G.n[1] - tl[1][b] * B.T[1]) + R : 1;
+        const int li = (wl[2][a] * W1 + wl[1][b]) * W0 + wl[0][c];
+        const float* src = B.wscr + (int64_t)t * 3 * B.wmax + li;
+        s0 += src[0];
+        s1 += src[B.wmax];
+        s2 += src[2 * B.wmax];
+      }
+  J0[idx] += s0;
+  J1[idx] += s1;
+  J2[idx] += s2;
+}
+
 template <int O, int DIM>
 __global__ __launch_bounds__(256) void k_halo_sum(KGrid G, KBins B, float* __restrict__ J0,
                                                   float* __restrict__ J1,
                                                   float* __restrict__ J2) {
-  constexpr int LO = TileWin<O, DIM>::LO, R = TileWin<O, DIM>::R;
   const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride) {
-    const int n3[3] = {(int)(idx % G.N[0]), (int)((idx / G.N[0]) % G.N[1]),
-                       (int)(idx / ((int64_t)G.N[0] * G.N[1]))};
-    int tl[3][6], wl[3][6], cnt[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      cnt[d] = 0;
-      if (d >= DIM) {
-        tl[d][0] = 0;
-        wl[d][0] = 0;
-        cnt[d] = 1;
-        continue;
-      }
-      if (G.per[d]) {
-        for (int k = -1; k <= 1; ++k)
-          cnt[d] = halo_cands(n3[d] + k * G.n[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d],
-                              cnt[d]);
-      } else {
-        cnt[d] = halo_cands(n3[d] - G.g[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d], cnt[d]);
-      }
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride)
+    halo_node<O, DIM>(G, B, J0, J1, J2, idx);
+}
+
+// Batched launches: blockIdx.y = patch.
+__global__ __launch_bounds__(256) void k_batched_prologue(const BatchPatch* __restrict__ pd,
+                                                          int* __restrict__ queue, unsigned flags) {
+  const BatchPatch& d = pd[blockIdx.y];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (flags & PIC_F_EMIT_MOVERS) {
+      d.B.ctr[CTR_NMOV] = 0;
+      d.B.ctr[CTR_NDROP] = 0;
     }
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
-    for (int a = 0; a < cnt[2]; ++a)
-      for (int b = 0; b < cnt[1]; ++b)
-        for (int c = 0; c < cnt[0]; ++c) {
-          const int t = tl[0][c] + B.nt[0] * (tl[1][b] + B.nt[1] * tl[2][a]);
-          const int W0 = min(B.T[0], G.n[0] - tl[0][c] * B.T[0]) + R;
-          const int W1 = DIM >= 2 ? min(B.T[1], G.n[1] - tl[1][b] * B.T[1]) + R : 1;
-          const int li = (wl[2][a] * W1 + wl[1][b]) * W0 + wl[0][c];
-          const float* src = B.wscr + (int64_t)t * 3 * B.wmax + li;
-          s0 += src[0];
-          s1 += src[B.wmax];
-          s2 += src[2 * B.wmax];
-        }
-    J0[idx] += s0;
-    J1[idx] += s1;
-    J2[idx] += s2;
+    if (blockIdx.y == 0) *queue = 0;
   }
+  if (flags & PIC_F_ACCUMULATE) return;
+  const int64_t tot = (int64_t)d.G.N[0] * d.G.N[1] * d.G.N[2];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += stride) {
+    d.J[0][i] = 0.0f;
+    d.J[1][i] = 0.0f;
+    d.J[2][i] = 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_batched_halo(const BatchPatch* __restrict__ pd) {
+  const BatchPatch& d = pd[blockIdx.y];
+  const int64_t tot = (int64_t)d.G.N[0] * d.G.N[1] * d.G.N[2];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int order = d.G.order;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride) {
+    if (order == 1) halo_node<1, 3>(d.G, d.B, d.J[0], d.J[1], d.J[2], idx);
+    else if (order == 2) halo_node<2, 3>(d.G, d.B, d.J[0], d.J[1], d.J[2], idx);
+    else halo_node<3, 3>(d.G, d.B, d.J[0], d.J[1], d.J[2], idx);
+  }
+}
+
+void batched_prologue_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, int* queue,
+                             unsigned flags, hipStream_t s) {
+  const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_nodes + 255) / 256, 512));
+  hipLaunchKernelGGL(k_batched_prologue, dim3(bx, npatch), dim3(256), 0, s, pd, queue, flags);
+}
+
+void batched_halo_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, hipStream_t s) {
+  const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_nodes + 255) / 256, 512));
+  hipLaunchKernelGGL(k_batched_halo, dim3(bx, npatch), dim3(256), 0, s, pd);
 }
 
 template <int O, int DIM>

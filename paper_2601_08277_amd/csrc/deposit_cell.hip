@@ -473,13 +473,12 @@ __device__ __forceinline__ void cv_consume(int k0, int k1, const float* sf, cons
 // unit u. Every wave walks the same units and passes the same number of barriers. (A
 // workgroup of more than four waves was measured to fit only once per CU.)
 template <int O, int DIM>
-__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 4) void k_dep_cell_valu(
-    KGrid G, KBins B, KPart P, float* __restrict__ J0, float* __restrict__ J1,
-    float* __restrict__ J2, unsigned flags, double dt) {
+__device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const KPart& P,
+                                          float* J0, float* J1, float* J2, unsigned flags,
+                                          double dt, int tile, unsigned char* smem_raw) {
   constexpr int NA = csz_max<O, DIM>();
-  extern __shared__ __align__(16) unsigned char smem_raw[];
   const CellLayout<O, DIM> L(B);
-  const TileBox tb = tile_box(G.n, B.T, B.nt, blockIdx.x);
+  const TileBox tb = tile_box(G.n, B.T, B.nt, tile);
   const TileWin<O, DIM> tw(tb);
   int32_t* s_off = (int32_t*)smem_raw;
   int32_t* s_len = s_off + tb.nb + 1;
@@ -552,7 +551,40 @@ __global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 4) void k_dep_cell_valu(
   }
   if (bad) atomicOr(B.err, bad);
   __syncthreads();
-  store_window(B, blockIdx.x, tw, win, blockDim.x, threadIdx.x);
+  store_window(B, tile, tw, win, blockDim.x, threadIdx.x);
+}
+
+template <int O, int DIM>
+__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 4) void k_dep_cell_valu(
+    KGrid G, KBins B, KPart P, float* __restrict__ J0, float* __restrict__ J1,
+    float* __restrict__ J2, unsigned flags, double dt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cell_tile<O, DIM>(G, B, P, J0, J1, J2, flags, dt, blockIdx.x, smem_raw);
+}
+
+// Persistent batched deposition (3D patches, any order): each workgroup pulls (patch,
+// tile) items from a device counter until the list is exhausted, so patches of uneven
+// size and order share one launch and the longest items (listed first) start first.
+__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 4) void k_dep_cell_batched(
+    const BatchPatch* __restrict__ pd, const int2* __restrict__ items, int nitems,
+    int* __restrict__ queue, unsigned flags) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= nitems) break;
+    const int pi = __builtin_amdgcn_readfirstlane(items[it].x);
+    const int tile = __builtin_amdgcn_readfirstlane(items[it].y);
+    const BatchPatch& d = pd[pi];
+    const int order = d.G.order;
+    if (order == 1) cell_tile<1, 3>(d.G, d.B, d.P, d.J[0], d.J[1], d.J[2], flags, d.dt, tile, smem_raw);
+    else if (order == 2) cell_tile<2, 3>(d.G, d.B, d.P, d.J[0], d.J[1], d.J[2], flags, d.dt, tile, smem_raw);
+    else cell_tile<3, 3>(d.G, d.B, d.P, d.J[0], d.J[1], d.J[2], flags, d.dt, tile, smem_raw);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -567,6 +599,31 @@ static bool launch_cell_valu(const KGrid& G, const KPart& P, pic_bins* b, float*
   hipLaunchKernelGGL((k_dep_cell_valu<O, DIM>), dim3(b->kb.ntiles), dim3(CV_WAVES * PIC_WAVE), smem,
                      s, G, b->kb, P, J0, J1, J2, flags, dt);
   return true;
+}
+
+size_t cell_smem_bytes(int order, int dim, const KBins& kb) {
+  if (dim == 3) {
+    if (order == 1) return CellLayout<1, 3>(kb).total;
+    if (order == 2) return CellLayout<2, 3>(kb).total;
+    return CellLayout<3, 3>(kb).total;
+  }
+  if (order == 1) return CellLayout<1, 2>(kb).total;
+  if (order == 2) return CellLayout<2, 2>(kb).total;
+  return CellLayout<3, 2>(kb).total;
+}
+
+int batched_blocks_per_cu(size_t smem) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dep_cell_batched, CV_WAVES * PIC_WAVE,
+                                                   smem) != hipSuccess)
+    nb = 1;
+  return nb < 1 ? 1 : nb;
+}
+
+void batched_cell_launch(const BatchPatch* pd, const int2* items, int nitems, int* queue,
+                         int blocks, size_t smem, unsigned flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_dep_cell_batched, dim3(blocks), dim3(CV_WAVES * PIC_WAVE), smem, s, pd,
+                     items, nitems, queue, flags);
 }
 
 int choose_path(const KGrid& G, const pic_bins* b) {

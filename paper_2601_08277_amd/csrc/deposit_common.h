@@ -193,6 +193,24 @@ __device__ __forceinline__ int halo_cands(int m, int n, int T, int nt, int LO, i
   return cnt;
 }
 
+// One patch of a batched launch, as the persistent kernels read it.
+struct BatchPatch {
+  KGrid G;
+  KBins B;
+  KPart P;
+  float* J[3];
+  double dt;
+};
+
+// Batched launches (deposit_cell.hip, deposit.hip).
+size_t cell_smem_bytes(int order, int dim, const KBins& kb);
+int batched_blocks_per_cu(size_t smem);
+void batched_cell_launch(const BatchPatch* pd, const int2* items, int nitems, int* queue,
+                         int blocks, size_t smem, unsigned flags, hipStream_t s);
+void batched_prologue_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, int* queue,
+                             unsigned flags, hipStream_t s);
+void batched_halo_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, hipStream_t s);
+
 // Path selection and the per-cell paths (deposit_cell.hip).
 int choose_path(const KGrid& G, const pic_bins* b);
 bool deposit_cell_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, float* J1,

@@ -65,6 +65,11 @@ void scan_exclusive_i32(pic_bins* b, int32_t* data, int64_t n, hipStream_t s);
 void reset_movers(pic_bins* b, hipStream_t s);
 void reset_step_counters(pic_bins* b, hipStream_t s);
 
+// Argument checks shared by the entry points (api.hip).
+pic_status validate_grid(const pic_grid* g);
+pic_status validate_particles(const pic_particles* p, int dim);
+bool same_grid(const pic_grid& a, const pic_grid& b);
+
 // Error reporting (api.hip).
 pic_status set_error(pic_status st, const std::string& msg);
 pic_status check_hip(hipError_t e, const char* what);

@@ -12,6 +12,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpic.so")
 
 PIC_OK = 0
+(PIC_ERR_INVALID_ARG, PIC_ERR_UNSUPPORTED, PIC_ERR_OUT_OF_DOMAIN, PIC_ERR_CAPACITY,
+ PIC_ERR_INVALID_PARTICLE, PIC_ERR_HIP) = -1, -2, -3, -4, -5, -6
 PIC_BC_PERIODIC, PIC_BC_GUARD = 0, 1
 PATH_AUTO, PATH_ATOMIC, PATH_CELL_VALU, PATH_MFMA_BF16, PATH_MFMA_FP16, PATH_UNSORTED = range(6)
 PATH_NAMES = {"auto": PATH_AUTO, "atomic": PATH_ATOMIC, "cell_valu": PATH_CELL_VALU,
@@ -23,7 +25,8 @@ INVALID_ID = -1
 EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "pic_bins_destroy",
            "pic_bins_get_view", "pic_bins_copy_tables", "pic_rebin", "pic_rebin_stats_read", "pic_bins_report_perf",
            "pic_deposit", "pic_deposit_backward", "pic_drift", "pic_plan_create",
-           "pic_plan_destroy", "pic_deposit_batched", "pic_check", "pic_last_error"]
+           "pic_plan_destroy", "pic_deposit_batched", "pic_plan_info", "pic_check",
+           "pic_last_error"]
 
 
 class PicError(RuntimeError):
@@ -276,6 +279,53 @@ def deposit(grid, parts, bins, path=PATH_AUTO, flags=0, J=None):
     _check(lib().pic_deposit(ctypes.byref(grid.c), ctypes.byref(pc), bins.h if bins else None,
                              _ptr(J[0]), _ptr(J[1]), _ptr(J[2]), path, flags, _stream()))
     return J
+
+
+class Plan:
+    """Batched deposition plan over independent 3D patches (pic_plan_create)."""
+
+    def __init__(self, grids, bins, tune_cache=None):
+        self.grids = list(grids)
+        self.bins = list(bins)
+        n = len(self.grids)
+        garr = (PicGrid * n)(*[g.c for g in self.grids])
+        barr = (ctypes.c_void_p * n)(*[b.h.value for b in self.bins])
+        h = ctypes.c_void_p()
+        path = tune_cache.encode() if tune_cache else None
+        _check(lib().pic_plan_create(garr, n, barr, path, ctypes.byref(h)))
+        self.h = h
+
+    def info(self):
+        ni, nb, bpc = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        lds = ctypes.c_int64()
+        _check(lib().pic_plan_info(self.h, ctypes.byref(ni), ctypes.byref(nb), ctypes.byref(bpc),
+                                   ctypes.byref(lds)))
+        return {"items": ni.value, "blocks": nb.value, "blocks_per_cu": bpc.value,
+                "lds_bytes": lds.value}
+
+    def close(self):
+        if self.h:
+            lib().pic_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def deposit_batched(plan, parts_list, J_list=None, path=PATH_AUTO, flags=0):
+    """Deposit every patch of `plan` in one persistent launch; returns the J lists."""
+    if isinstance(path, str):
+        path = PATH_NAMES[path]
+    n = len(parts_list)
+    if J_list is None:
+        J_list = [new_J(g) for g in plan.grids]
+    parr = (PicParticles * n)(*[p.c() for p in parts_list])
+    jarr = (ctypes.c_void_p * (3 * n))(*[J[c].data_ptr() for J in J_list for c in range(3)])
+    _check(lib().pic_deposit_batched(plan.h, parr, jarr, path, flags, _stream()))
+    return J_list
 
 
 def deposit_backward(grid, parts, bins, G, want_dw=True):
