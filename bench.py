@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--tile", default="8x8x4", help="particle tile, cells (x by y by z)")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
+                    help="c2: 128^3 uniform step (default); c3: 256x256x1024 LWFA snapshot; "
+                         "c4: 64 batched patches (graph replay); c5: 64^3 forward + backward")
+    ap.add_argument("--patches", type=int, default=64, help="c4: number of patches")
     ap.add_argument("--calib-copy", action="store_true",
                     help="end with one plain 256 MiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -78,6 +82,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.workload != "c2":
+        out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args, torch, pic, synth)
+        print(json.dumps(out), flush=True)
+        return
     n3 = (args.n, args.n, args.n)
     params, arrays = synth.c2(n=n3, ppc=args.ppc)
     N = arrays["x"].size
@@ -174,6 +182,145 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out), flush=True)
+
+
+def _events_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _common(args, metric, value, unit, ms, config, dtype="f32"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+            "config": config}
+
+
+def bench_c3(args, torch, pic, synth):
+    """Static deposition of the 256x256x1024 laser-wakefield-shaped snapshot, every path."""
+    params, arrays = synth.c3()
+    N = arrays["x"].size
+    grid = pic.Grid(params)
+    ncell = 256 * 256 * 1024
+    slots = pic.slots_for(N, ncell, 0.25)
+    parts = pic.Particles.from_arrays(arrays, slots)
+    del arrays
+    tile = tuple(int(t) for t in args.tile.split("x"))
+    bins = pic.Bins(grid, tile, 0.25, slots)
+    pic.rebin(grid, parts, bins, pic.REBIN_FULL)
+    J = pic.new_J(grid)
+    res = {}
+    for name in ("cell_valu", "mfma_bf16", "mfma_fp16", "atomic"):
+        ms = _events_ms(torch, lambda: pic.deposit(grid, parts, bins, name, 0, J=J), args.steps)
+        res[name] = {"kernel_ms": ms, "particles_per_s": N / (ms * 1e-3)}
+    bins.check()
+    bins.close()
+    best = min(res, key=lambda k: res[k]["kernel_ms"])
+    ms = res[best]["kernel_ms"]
+    byts = N * 40 + ncell * 12
+    out = _common(args, "particles deposited/s, order-3 3D LWFA snapshot", N / (ms * 1e-3),
+                  "particles/s", ms,
+                  {"workload": "LWFA-shaped 256x256x1024, order 3, periodic x/y, guard z; static "
+                               "deposition (J overwritten)", "particles": int(N), "cells": ncell,
+                   "path": best, "tile": list(tile)})
+    out["roofline"] = {"bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "traffic": None, "kernel": f"pic_deposit call ({best})",
+                       "bytes_per_launch": byts, "kernel_ms": ms}
+    out["paths"] = res
+    return out
+
+
+def bench_c4(args, torch, pic, synth):
+    """64 uneven patches (edges 32..96, ppc lognormal, orders 1-3) in one persistent
+    batched launch, captured in a HIP graph; times the graph replay."""
+    from paper_2601_08277_amd import autotune
+    cache_path = os.path.join(ROOT, "paper_2601_08277_amd", "tune_cache.json")
+    cache = autotune.load(cache_path) if os.path.exists(cache_path) else {"entries": []}
+    patches = synth.c4_patches(npatch=args.patches)
+    grids, parts, bins, Js = [], [], [], []
+    N = 0
+    for params, arrays in patches:
+        g = pic.Grid(params)
+        tile = autotune.lookup(cache, params["order"], params["ppc"])[0]
+        n = arrays["x"].size
+        N += n
+        slots = pic.slots_for(n, int(np.prod(params["n"])), 0.25)
+        p = pic.Particles.from_arrays(arrays, slots)
+        b = pic.Bins(g, tile, 0.25, slots)
+        pic.rebin(g, p, b, pic.REBIN_FULL)
+        grids.append(g)
+        parts.append(p)
+        bins.append(b)
+        Js.append(pic.new_J(g))
+    del patches
+    plan = pic.Plan(grids, bins, tune_cache=cache_path if os.path.exists(cache_path) else None)
+    pic.deposit_batched(plan, parts, Js)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        pic.deposit_batched(plan, parts, Js)
+    torch.cuda.synchronize()
+    ms = _events_ms(torch, graph.replay, args.steps)
+    for b in bins:
+        b.check()
+    info = plan.info()
+    plan.close()
+    for b in bins:
+        b.close()
+    ncell = int(sum(np.prod(g.params["n"]) for g in grids))
+    byts = N * 40 + ncell * 12
+    out = _common(args, "particles deposited/s, batched uneven patches (graph replay)",
+                  N / (ms * 1e-3), "particles/s", ms,
+                  {"workload": f"{args.patches} patches, edges U{{32..96}}, ppc lognormal(ln 8, 1) "
+                               f"clipped to [1, 64], orders U{{1,2,3}}, guard BC; one persistent "
+                               f"launch per replay", "particles": int(N), "cells": ncell,
+                   "path": "cell_valu", "plan": info})
+    out["roofline"] = {"bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "traffic": None, "kernel": "graph: zero + k_dep_cell_batched + halo",
+                       "bytes_per_launch": byts, "kernel_ms": ms}
+    return out
+
+
+def bench_c5(args, torch, pic, synth):
+    """64^3 x 8 order 3: forward deposition and the adjoint gather (pic_deposit_backward)."""
+    params, arrays = synth.c5()
+    N = arrays["x"].size
+    grid = pic.Grid(params)
+    ncell = 64 ** 3
+    slots = pic.slots_for(N, ncell, 0.25)
+    parts = pic.Particles.from_arrays(arrays, slots)
+    tile = tuple(int(t) for t in args.tile.split("x"))
+    bins = pic.Bins(grid, tile, 0.25, slots)
+    pic.rebin(grid, parts, bins, pic.REBIN_FULL)
+    G = [torch.from_numpy(g).cuda() for g in synth.adjoint_field(grid.shape)]
+    J = pic.new_J(grid)
+    fwd = _events_ms(torch, lambda: pic.deposit(grid, parts, bins, "auto", 0, J=J), args.steps)
+    bwd = _events_ms(torch, lambda: pic.deposit_backward(grid, parts, bins, G), args.steps)
+    bins.close()
+    byts = N * (40 + 28) + ncell * 12
+    out = _common(args, "particles/s through the adjoint gather, order-3 3D", N / (bwd * 1e-3),
+                  "particles/s", bwd,
+                  {"workload": "64^3 periodic, 8 per cell, order 3; pic_deposit_backward with "
+                               "G ~ N(0,1) (cache-resident: 137 MB)", "particles": int(N),
+                   "cells": ncell, "tile": list(tile)})
+    out["roofline"] = {"bound": "hbm", "achieved": byts / (bwd * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": byts / (bwd * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "traffic": None, "kernel": "k_backward<3,3>", "bytes_per_launch": byts,
+                       "kernel_ms": bwd}
+    out["forward_ms"] = fwd
+    out["forward_plus_backward_ms"] = fwd + bwd
+    return out
 
 
 def path_table(pic, torch, grid, parts, bins, N, ncell):
