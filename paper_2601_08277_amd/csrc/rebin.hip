@@ -155,34 +155,71 @@ __device__ __forceinline__ int32_t bin_of_pos(const KGrid& G, const KBins& B, do
 }
 
 // ---- FULL ------------------------------------------------------------------------
+// Runs of equal keys among the 64 lanes of a wave (consecutive slots): the run's first lane,
+// this lane's position in the run and the run length. Between global sorts most particles
+// still sit in their bin, so consecutive slots mostly share a bin and one atomic per run
+// replaces one per particle.
+__device__ __forceinline__ void wave_runs(int32_t key, int& head, int& pos, int& len) {
+  const int lane = __lane_id();
+  const int32_t prev = __shfl_up(key, 1);
+  const bool is_head = lane == 0 || prev != key;
+  const unsigned long long hm = __ballot(is_head);
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  head = 63 - __builtin_clzll(hm & upto);
+  const unsigned long long above = hm & ~upto;
+  const int next = above ? __builtin_ctzll(above) : 64;
+  pos = lane - head;
+  len = next - head;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* s_part) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x / PIC_WAVE;
+  __syncthreads();
+  if (__lane_id() == 0) s_part[w] = v;
+  __syncthreads();
+  T t = 0;
+  for (int i = 0; i < (int)(blockDim.x / PIC_WAVE); ++i) t += s_part[i];
+  return t;
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void k_full_count(KGrid G, KBins B, KPart P,
                                                     int32_t* __restrict__ sbin) {
+  __shared__ int32_t s_part[4];
   uint32_t bad = 0;
+  int32_t counted = 0;
   const int stride = gridDim.x * blockDim.x;
-  // uniform trip count so every lane reaches the wave-level count below
+  // uniform trip count: every lane reaches the wave-level run detection
   for (int base = blockIdx.x * blockDim.x; base < P.nslots; base += stride) {
-    int s = base + threadIdx.x;
+    const int s = base + threadIdx.x;
     int32_t bn = -1;
-    if (s < P.nslots && P.id[s] != PIC_INVALID_ID) {
+    if (s < P.nslots && P.id[s] != PIC_INVALID_ID)
       bn = bin_of_pos<DIM>(G, B, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, bad);
-      if (bn >= 0) atomicAdd(&B.len[bn], 1);
-    }
     if (s < P.nslots) sbin[s] = bn;
-    (void)wave_append(bn >= 0, &B.ctr[CTR_TOTAL]);
+    int head, pos, len;
+    wave_runs(bn, head, pos, len);
+    if (bn >= 0 && pos == 0) atomicAdd(&B.len[bn], len);
+    counted += bn >= 0 ? 1 : 0;
   }
+  const int32_t tot = block_sum(counted, s_part);
+  if (threadIdx.x == 0 && tot) atomicAdd(&B.ctr[CTR_TOTAL], tot);
   if (bad) atomicOr(B.err, bad);
 }
 
 __global__ __launch_bounds__(256) void k_full_extra(KBins B, double slack,
                                                     unsigned long long* desired) {
+  __shared__ unsigned long long s_part[4];
   unsigned long long acc = 0;
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B.nbins; b += gridDim.x * blockDim.x) {
     int32_t e = (int32_t)ceil(slack * (double)B.len[b]);
     B.ins_cnt[b] = e;
     acc += (unsigned long long)e;
   }
-  if (acc) atomicAdd(desired, acc);
+  const unsigned long long tot = block_sum(acc, s_part);
+  if (threadIdx.x == 0 && tot) atomicAdd(desired, tot);
 }
 
 __global__ __launch_bounds__(256) void k_full_caps(KBins B, int32_t nslots,
@@ -202,35 +239,69 @@ __global__ __launch_bounds__(256) void k_full_caps(KBins B, int32_t nslots,
   }
 }
 
-__global__ __launch_bounds__(256) void k_gap_fill(KPart D, int32_t lo, int32_t hi) {
-  for (int s = lo + blockIdx.x * blockDim.x + threadIdx.x; s < hi; s += gridDim.x * blockDim.x)
-    set_gap(D, s);
-}
-
+// Payload of every counted particle to its bin in the staging arrays; the rank inside the
+// bin comes from one atomic per run of equal bins.
 __global__ __launch_bounds__(256) void k_full_scatter(KBins B, KPart P, KPart S,
                                                       const int32_t* __restrict__ sbin) {
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.nslots; s += gridDim.x * blockDim.x) {
-    int32_t bn = sbin[s];
-    if (bn < 0) continue;
-    int r = atomicAdd(&B.ins_cnt[bn], 1);
-    copy_slot(S, B.off[bn] + r, P, s);
+  const int stride = gridDim.x * blockDim.x;
+  for (int base = blockIdx.x * blockDim.x; base < P.nslots; base += stride) {
+    const int s = base + threadIdx.x;
+    const int32_t bn = s < P.nslots ? sbin[s] : -1;
+    int head, pos, len;
+    wave_runs(bn, head, pos, len);
+    int r = 0;
+    if (bn >= 0 && pos == 0) r = atomicAdd(&B.ins_cnt[bn], len);
+    r = __shfl(r, head);
+    if (bn >= 0) copy_slot(S, B.off[bn] + r + pos, P, s);
   }
 }
 
-__global__ __launch_bounds__(256) void k_full_sort_bins(KBins B, KPart S) {
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B.nbins; b += gridDim.x * blockDim.x) {
-    int n = B.len[b];
-    if (n >= 2) sort_range_by_id(S, B.off[b], n);
+// Final placement in two passes. Ranks, one thread per bin: the staged particle j of bin b
+// goes to its rank by id inside the bin (a deterministic order whatever order the
+// scatter's atomics produced); src[o + rank] = o + j, and -1 on the bin's gap slots.
+__global__ __launch_bounds__(256) void k_full_rank(KBins B, KPart S, int32_t* __restrict__ src) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B.nbins; b += stride) {
+    const int o = B.off[b], n = B.len[b], cap = B.off[b + 1] - o;
+    if (n <= 16) {
+      int32_t ids[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) ids[k] = k < n ? S.id[o + k] : INT32_MAX;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        if (j < n) {
+          int r = 0;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) r += ids[k] < ids[j] ? 1 : 0;
+          src[o + r] = o + j;
+        }
+      }
+    } else {
+      for (int j = 0; j < n; ++j) {
+        const int32_t idj = S.id[o + j];
+        int r = 0;
+        for (int k = 0; k < n; ++k) r += S.id[o + k] < idj ? 1 : 0;
+        src[o + r] = o + j;
+      }
+    }
+    for (int j = n; j < cap; ++j) src[o + j] = -1;
     B.ins_cnt[b] = 0;
     B.moved_out[b] = 0;
   }
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < B.ntiles; t += gridDim.x * blockDim.x)
-    B.tile_flag[t] = 0;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int t = tid; t < B.ntiles; t += stride) B.tile_flag[t] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_copy_part(KPart D, KPart S, int32_t n) {
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x)
-    copy_slot(D, s, S, s);
+// Copy, lanes = destination slots (coalesced writes): particle arrays <- staged payload,
+// gaps where src is -1 and past the last bin.
+__global__ __launch_bounds__(256) void k_full_place(KBins B, KPart P, KPart S,
+                                                    const int32_t* __restrict__ src) {
+  const int used = B.off[B.nbins];
+  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < P.nslots; d += gridDim.x * blockDim.x) {
+    const int j = d < used ? src[d] : -1;
+    if (j >= 0) copy_slot(P, d, S, j);
+    else set_gap(P, d);
+  }
 }
 
 __global__ void k_full_finish(KBins B) {
@@ -250,25 +321,24 @@ void rebin_full(pic_bins* b, const KGrid& G, const KPart& P, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, B.ctr + CTR_TOTAL, (int64_t)1);
   if (ns > 0) {
     if (G.dim == 3)
-      hipLaunchKernelGGL(k_full_count<3>, dim3(grid_for(ns)), dim3(256), 0, s, G, B, P, b->sbin);
+      hipLaunchKernelGGL(k_full_count<3>, dim3(grid_for(ns, 4096)), dim3(256), 0, s, G, B, P, b->sbin);
     else
-      hipLaunchKernelGGL(k_full_count<2>, dim3(grid_for(ns)), dim3(256), 0, s, G, B, P, b->sbin);
+      hipLaunchKernelGGL(k_full_count<2>, dim3(grid_for(ns, 4096)), dim3(256), 0, s, G, B, P, b->sbin);
   }
-  hipLaunchKernelGGL(k_full_extra, dim3(grid_for(B.nbins)), dim3(256), 0, s, B, b->slack,
+  hipLaunchKernelGGL(k_full_extra, dim3(grid_for(B.nbins, 2048)), dim3(256), 0, s, B, b->slack,
                      &b->dctr->desired);
   hipLaunchKernelGGL(k_full_caps, dim3(grid_for(B.nbins + 1)), dim3(256), 0, s, B, (int32_t)ns,
                      &b->dctr->desired);
   scan_exclusive_i32(b, B.off, B.nbins + 1, s);
-  if (ns > 0) {
-    hipLaunchKernelGGL(k_gap_fill, dim3(grid_for(ns)), dim3(256), 0, s, b->scratch, 0, (int32_t)ns);
-    zero_i32(B.ins_cnt, B.nbins, s);
-    hipLaunchKernelGGL(k_full_scatter, dim3(grid_for(ns)), dim3(256), 0, s, B, P, b->scratch,
-                       b->sbin);
-  }
-  hipLaunchKernelGGL(k_full_sort_bins, dim3(grid_for(std::max<int64_t>(B.nbins, B.ntiles))),
-                     dim3(256), 0, s, B, b->scratch);
+  zero_i32(B.ins_cnt, B.nbins, s);
   if (ns > 0)
-    hipLaunchKernelGGL(k_copy_part, dim3(grid_for(ns)), dim3(256), 0, s, P, b->scratch, (int32_t)ns);
+    hipLaunchKernelGGL(k_full_scatter, dim3(grid_for(ns, 4096)), dim3(256), 0, s, B, P, b->scratch,
+                       b->sbin);
+  hipLaunchKernelGGL(k_full_rank, dim3(grid_for(std::max<int64_t>(B.nbins, B.ntiles))),
+                     dim3(256), 0, s, B, b->scratch, b->sbin);
+  if (ns > 0)
+    hipLaunchKernelGGL(k_full_place, dim3(grid_for(ns, 8192)), dim3(256), 0, s, B, P, b->scratch,
+                       b->sbin);
   hipLaunchKernelGGL(k_full_finish, dim3(1), dim3(64), 0, s, B);
 }
 
@@ -424,15 +494,22 @@ __global__ __launch_bounds__(256) void k_rebuild(KGrid G, KBins B, KPart P, KPar
     acc += s_len[i] + per + (i < rem ? 1 : 0);
   }
   if (threadIdx.x == 0) s_new[tb.nb] = S1;
-  // staging: gaps everywhere, then each bin's particles at their new place
-  for (int s = S0 + threadIdx.x; s < S1; s += blockDim.x) set_gap(S, s);
+  // stage the tile's slots as they are, then write every slot of the new layout from the
+  // staging copy (lanes = slots in both passes; the new bin of a slot by binary search)
+  for (int s = S0 + threadIdx.x; s < S1; s += blockDim.x) copy_slot(S, s, P, s);
   __threadfence_block();
   __syncthreads();
-  for (int i = threadIdx.x; i < tb.nb; i += blockDim.x)
-    for (int k = 0; k < s_len[i]; ++k) copy_slot(S, s_new[i] + k, P, s_off[i] + k);
-  __threadfence_block();
-  __syncthreads();
-  for (int s = S0 + threadIdx.x; s < S1; s += blockDim.x) copy_slot(P, s, S, s);
+  for (int d = S0 + threadIdx.x; d < S1; d += blockDim.x) {
+    int lo = 0, hi = tb.nb;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_new[mid] <= d) lo = mid;
+      else hi = mid;
+    }
+    const int k = d - s_new[lo];
+    if (k < s_len[lo]) copy_slot(P, d, S, s_off[lo] + k);
+    else set_gap(P, d);
+  }
   for (int i = threadIdx.x; i < tb.nb; i += blockDim.x) B.off[tb.b0 + i] = s_new[i];
   if (threadIdx.x == 0) {
     B.tile_flag[t] = 0;
