@@ -66,8 +66,8 @@ struct StaleRec {
 };
 
 // LDS layout of one workgroup (bytes): bin offsets and lengths | tile window (3 comps)
-// | two stage buffers f[3][CAP], a[3][CAP] | per producer: slot -> cell map and mover
-// buffer | stale list and its count.
+// | two stage buffers f[3][CAP], a[3][CAP] | per producer: slot -> cell map | per
+// consumer: mover buffer | stale list and its count.
 template <int O, int DIM>
 struct CellLayout {
   size_t win_off, stage_off, map_off, mb_off, stale_off, total;
@@ -76,7 +76,7 @@ struct CellLayout {
     stage_off = win_off + (((size_t)3 * TileWin<O, DIM>::max_size(kb) * sizeof(float) + 15) & ~(size_t)15);
     map_off = stage_off + (size_t)2 * 6 * CV_CAP * sizeof(float);
     mb_off = map_off + (size_t)CV_PROD * CV_MAPW;
-    stale_off = mb_off + (size_t)CV_PROD * 3 * MBUF * sizeof(int32_t);
+    stale_off = mb_off + (size_t)CV_CONS * 3 * MBUF * sizeof(int32_t);
     total = stale_off + (size_t)CV_STALE * sizeof(StaleRec) + 16;
   }
 };
@@ -184,13 +184,10 @@ template <int O, int DIM>
 __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const KPart& P,
                                          const TileBox& tb, const int32_t* s_off,
                                          const int32_t* s_len, const CellGroup& gr, float* sf,
-                                         float* sa, int8_t* map, MoverBuf& mb, StaleRec* stale,
-                                         int* s_nstale, float* const* J, unsigned flags,
-                                         double dt, uint32_t& bad) {
+                                         float* sa, int8_t* map, StaleRec* stale, int* s_nstale,
+                                         float* const* J, uint32_t& bad) {
   const int lane = threadIdx.x % PIC_WAVE;
   const int pw = threadIdx.x / PIC_WAVE - CV_CONS;   // producer index
-  const bool emit = flags & PIC_F_EMIT_MOVERS;
-  const bool drift = flags & PIC_F_DRIFT;
   const int ex = tb.e[0], exy = tb.e[0] * tb.e[1];
   for (int lo = gr.S0; lo < gr.S1; lo += CV_MAPW) {
     const int hi = min(gr.S1, lo + CV_MAPW);
@@ -220,11 +217,17 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
         r.w = P.w[r.s];
       }
     };
-    CvRaw nxt;
-    if (first < hi) fetch(first, nxt);
+    // three chunks in flight ahead of the one being processed (memory latency, not the
+    // VALU, bounds this wave)
+    CvRaw nx1, nx2, nx3;
+    if (first < hi) fetch(first, nx1);
+    if (first + step < hi) fetch(first + step, nx2);
+    if (first + 2 * step < hi) fetch(first + 2 * step, nx3);
     for (int base = first; base < hi; base += step) {
-      const CvRaw r = nxt;
-      if (base + step < hi) fetch(base + step, nxt);
+      const CvRaw r = nx1;
+      nx1 = nx2;
+      nx2 = nx3;
+      if (base + 3 * step < hi) fetch(base + 3 * step, nx3);
       const int lb = gr.g0 + (r.lc < 0 ? 0 : r.lc);
       PartPrep<O, DIM> p;
       double pos[3] = {r.x, r.y, r.z};
@@ -269,32 +272,6 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
           sf[d * CV_CAP + r.si] = mine ? p.f[d] : 0.0f;
           sa[d * CV_CAP + r.si] = mine ? p.amp[d] : 0.0f;
         }
-      }
-      if (ok && drift) {
-        float ux = r.ux, uy = r.uy, uz = r.uz;
-        drift_one<DIM>(G, pos, ux, uy, uz, dt);
-        P.x[r.s] = pos[0];
-        P.y[r.s] = pos[1];
-        if (DIM == 3) P.z[r.s] = pos[2];
-      }
-      if (emit) {
-        // mover: its (new) cell differs from the cell of the bin it sits in
-        bool mv = false;
-        int32_t nbn = -1;
-        if (ok) {
-          int c2[3];
-          float f2[3];
-          if (prep_cell<DIM>(G, pos[0], pos[1], pos[2], c2, f2, bad)) {
-            const int lx = c2[0] - tb.c0[0], ly = c2[1] - tb.c0[1];
-            const int lz = DIM == 3 ? c2[2] - tb.c0[2] : 0;
-            const bool in = (unsigned)lx < (unsigned)tb.e[0] && (unsigned)ly < (unsigned)tb.e[1] &&
-                            (unsigned)lz < (unsigned)(DIM == 3 ? tb.e[2] : 1);
-            const int loc = lx + ex * (ly + tb.e[1] * lz);
-            mv = !(in && loc == lb);
-            if (mv) nbn = in ? tb.b0 + loc : bin_of_cell(G.n, B.T, c2[0], c2[1], c2[2]);
-          }
-        }
-        mb_append(mb, B, mv, r.s, tb.b0 + lb, nbn);
       }
     }
   }
@@ -456,6 +433,67 @@ __device__ __forceinline__ void cv_flush_group(const TileBox& tb, const TileWin<
   else cv_flush<O, DIM, C, false>(tw, cc, acc, win, o);
 }
 
+// Consumer wave c, after accumulating a unit: the fused drift (x += v dt, FP64) and mover
+// detection (stage 1 of Alg. 2) for every third 64-slot chunk of the unit's slots, lanes =
+// slots. A slot's bin comes from a binary search over the group's 64 bin offsets; it is
+// done here rather than in the producer, whose loads bound the unit pipeline.
+template <int DIM>
+__device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, const KPart& P,
+                                              const TileBox& tb, const int32_t* s_off,
+                                              const int32_t* s_len, const CellGroup& gr,
+                                              int wave, MoverBuf& mb, unsigned flags, double dt,
+                                              uint32_t& bad) {
+  const int lane = threadIdx.x % PIC_WAVE;
+  const bool emit = flags & PIC_F_EMIT_MOVERS;
+  const bool drift = flags & PIC_F_DRIFT;
+  const int ex = tb.e[0];
+  for (int base = gr.S0 + wave * PIC_WAVE; base < gr.S1; base += CV_CONS * PIC_WAVE) {
+    const int s = base + lane;
+    int lo = 0, hi = gr.gn;
+    if (s < gr.S1) {
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[gr.g0 + mid] <= s) lo = mid;
+        else hi = mid;
+      }
+    }
+    const int k = s - s_off[gr.g0 + lo];
+    const int si = __shfl(gr.st, lo) + k - gr.R0;
+    const bool in_unit = s < gr.S1 && k < s_len[gr.g0 + lo] && si >= 0 && si < CV_CAP;
+    const int lb = gr.g0 + lo;
+    bool ok = false, mv = false;
+    int32_t nbn = -1;
+    if (in_unit) {
+      double pos[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
+      int c1[3];
+      float f1[3];
+      uint32_t nb0 = 0;   // errors are reported by the producer
+      ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], c1, f1, nb0);
+      if (ok && drift) {
+        drift_one<DIM>(G, pos, P.ux[s], P.uy[s], P.uz[s], dt);
+        P.x[s] = pos[0];
+        P.y[s] = pos[1];
+        if (DIM == 3) P.z[s] = pos[2];
+      }
+      if (ok && emit) {
+        // mover: its (new) cell differs from the cell of the bin it sits in
+        int c2[3];
+        float f2[3];
+        if (prep_cell<DIM>(G, pos[0], pos[1], pos[2], c2, f2, bad)) {
+          const int lx = c2[0] - tb.c0[0], ly = c2[1] - tb.c0[1];
+          const int lz = DIM == 3 ? c2[2] - tb.c0[2] : 0;
+          const bool in = (unsigned)lx < (unsigned)tb.e[0] && (unsigned)ly < (unsigned)tb.e[1] &&
+                          (unsigned)lz < (unsigned)(DIM == 3 ? tb.e[2] : 1);
+          const int loc = lx + ex * (ly + tb.e[1] * lz);
+          mv = !(in && loc == lb);
+          if (mv) nbn = in ? tb.b0 + loc : bin_of_cell(G.n, B.T, c2[0], c2[1], c2[2]);
+        }
+      }
+    }
+    if (emit) mb_append(mb, B, mv, s, tb.b0 + lb, nbn);
+  }
+}
+
 template <int O, int DIM, int C>
 __device__ __forceinline__ void cv_consume(int k0, int k1, const float* sf, const float* sa,
                                            float* acc, bool last, const TileBox& tb,
@@ -489,7 +527,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   const bool producer = wave >= CV_CONS;
   const int pw = producer ? wave - CV_CONS : 0;
   int8_t* map_p = (int8_t*)(smem_raw + L.map_off) + pw * CV_MAPW;
-  int32_t* mbb = (int32_t*)(smem_raw + L.mb_off) + pw * 3 * MBUF;
+  int32_t* mbb = (int32_t*)(smem_raw + L.mb_off) + (producer ? 0 : wave) * 3 * MBUF;
   StaleRec* stale = (StaleRec*)(smem_raw + L.stale_off);
   int* s_nstale = (int*)(smem_raw + L.stale_off + CV_STALE * sizeof(StaleRec));
   float* J[3] = {J0, J1, J2};
@@ -506,22 +544,21 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   // accumulators are not live across the producer's code.
   if (producer) {
     if (cur.g0 < tb.nb)
-      cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, map_p, mb, stale,
-                       s_nstale, J, flags, dt, bad);
+      cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, map_p, stale,
+                       s_nstale, J, bad);
     __syncthreads();
     int ub = 0;
     while (cur.g0 < tb.nb) {
       const CellGroup nxt = cv_next_unit(cur, s_off, s_len, tb.nb, lane);
       if (nxt.g0 < tb.nb) {
         float* nf = stage + (ub ^ 1) * 6 * CV_CAP;
-        cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, map_p, mb, stale,
-                         s_nstale, J, flags, dt, bad);
+        cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, map_p, stale,
+                         s_nstale, J, bad);
       }
       __syncthreads();
       cur = nxt;
       ub ^= 1;
     }
-    if (flags & PIC_F_EMIT_MOVERS) mb_flush(mb, B);
   } else {
     float acc[NA];
 #pragma unroll
@@ -537,10 +574,13 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
       if (wave == 0) cv_consume<O, DIM, 0>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       else if (wave == 1) cv_consume<O, DIM, 1>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       else cv_consume<O, DIM, 2>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
+      if (flags & (PIC_F_DRIFT | PIC_F_EMIT_MOVERS))
+        cv_drift_unit<DIM>(G, B, P, tb, s_off, s_len, cur, wave, mb, flags, dt, bad);
       __syncthreads();
       cur = nxt;
       ub ^= 1;
     }
+    if (flags & PIC_F_EMIT_MOVERS) mb_flush(mb, B);
   }
   __syncthreads();
   const int ns = min(*s_nstale, CV_STALE);
@@ -555,7 +595,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
 }
 
 template <int O, int DIM>
-__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 4) void k_dep_cell_valu(
+__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 3) void k_dep_cell_valu(
     KGrid G, KBins B, KPart P, float* __restrict__ J0, float* __restrict__ J1,
     float* __restrict__ J2, unsigned flags, double dt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -565,7 +605,7 @@ __global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 4) void k_dep_cell_valu(
 // Persistent batched deposition (3D patches, any order): each workgroup pulls (patch,
 // tile) items from a device counter until the list is exhausted, so patches of uneven
 // size and order share one launch and the longest items (listed first) start first.
-__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 4) void k_dep_cell_batched(
+__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 3) void k_dep_cell_batched(
     const BatchPatch* __restrict__ pd, const int2* __restrict__ items, int nitems,
     int* __restrict__ queue, unsigned flags) {
   extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -52,6 +52,13 @@ struct TileWin {
   __device__ __forceinline__ int index(int c, int mx, int my, int mz) const {
     return c * size + ((mz - o[2]) * W[1] + (my - o[1])) * W[0] + (mx - o[0]);
   }
+
+  __device__ __forceinline__ bool fits_cell(const int* cell) const {
+    bool in = true;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) in = in && cell[d] >= c0[d] && cell[d] < c0[d] + e[d];
+    return in;
+  }
 };
 
 // Window of a slab of the tile: planes [s0, s1) along the slowest used dimension
@@ -92,7 +99,7 @@ struct SubWin {
 // Per-wave mover buffer in LDS: movers are appended with a ballot and a lane prefix
 // count and copied to the global list, with one global atomic per flush, when it fills
 // and at the end of the tile (usually once per tile: the list counter is contended).
-constexpr int MBUF = 256;
+constexpr int MBUF = 128;
 
 struct MoverBuf {
   int32_t* slot;

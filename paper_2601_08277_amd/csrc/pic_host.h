@@ -49,6 +49,9 @@ struct pic_bins {
   bool perf_baseline_pending = true;
 };
 
+// Zero fill of int32 device memory (rebin.hip).
+__global__ void k_zero_i32(int32_t* p, int64_t n);
+
 // Launchers (implemented in rebin.hip / deposit.hip / backward.hip).
 KGrid make_kgrid(const pic_grid& g);
 KPart make_kpart(const pic_particles& p);
