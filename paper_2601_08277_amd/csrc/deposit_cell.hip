@@ -57,6 +57,9 @@ constexpr int CV_CONS = 3;      // consumer waves, one per current component
 constexpr int CV_PROD = 1;      // producer waves
 constexpr int CV_WAVES = CV_CONS + CV_PROD;
 constexpr int CV_STALE = 128;   // stale particles a tile keeps for the end phase
+// Staged amplitudes carry 1/6^DIM at third order: the consumers use weights times 6.
+template <int O, int DIM>
+constexpr float CV_AMP_SCALE = O == 3 ? (DIM == 3 ? 1.0f / 216.0f : 1.0f / 36.0f) : 1.0f;
 
 // A particle found in the bin of another cell, kept for the end phase.
 struct StaleRec {
@@ -234,7 +237,7 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
       bool ok = false, mine = false;
       if (r.lc >= 0) {
         ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad);
-        prep_amp(G.q, r.ux, r.uy, r.uz, r.w, p.amp);
+        prep_amp_rsq(G.q, r.ux, r.uy, r.uz, r.w, 1.0f, p.amp);
         // the particle's cell relative to the tile -> local bin (no division)
         const int lx = p.cell[0] - tb.c0[0], ly = p.cell[1] - tb.c0[1];
         const int lz = DIM == 3 ? p.cell[2] - tb.c0[2] : 0;
@@ -270,11 +273,19 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           sf[d * CV_CAP + r.si] = mine ? p.f[d] : 0.0f;
-          sa[d * CV_CAP + r.si] = mine ? p.amp[d] : 0.0f;
+          sa[d * CV_CAP + r.si] = mine ? p.amp[d] * CV_AMP_SCALE<O, DIM> : 0.0f;
         }
       }
     }
   }
+}
+
+// Shape weights as the consumers use them (third order: times 6, see CV_AMP_SCALE). In 2D
+// the z weight is the constant 1 and is not scaled.
+template <int O, bool STAG>
+__device__ __forceinline__ int cv_shape(float f, float* w) {
+  if constexpr (O == 3) return shape_w6<STAG>(f, w);
+  else return shape_w<O, STAG>(f, w);
 }
 
 // Accumulate component C of the lane's cell from the staged particles [k0, k1).
@@ -294,12 +305,12 @@ __device__ __forceinline__ void cv_accumulate(int k0, int k1, const float* sf, c
     float wx[5], wy[5], wz[5];
     {
       float w[O + 1];
-      int sh = shape_w<O, C == 0>(f[0], w);
+      int sh = cv_shape<O, C == 0>(f[0], w);
       pad_w<O, WX>(w, sh, wx);
-      sh = shape_w<O, C == 1>(f[1], w);
+      sh = cv_shape<O, C == 1>(f[1], w);
       pad_w<O, WY>(w, sh, wy);
       if constexpr (DIM == 3) {
-        sh = shape_w<O, C == 2>(f[2], w);
+        sh = cv_shape<O, C == 2>(f[2], w);
         pad_w<O, WZ>(w, sh, wz);
       } else {
         wz[0] = 1.0f;

@@ -40,6 +40,17 @@ __device__ __forceinline__ void prep_amp(float q, float ux, float uy, float uz, 
   amp[2] = qw * uz;
 }
 
+// The same amplitudes with the hardware reciprocal square root (about 1 ulp), times
+// `scale`: for staging, where the rsq's error is far below the float32 tolerance.
+__device__ __forceinline__ void prep_amp_rsq(float q, float ux, float uy, float uz, float w,
+                                             float scale, float* amp) {
+  const float ig = __builtin_amdgcn_rsqf(1.0f + (ux * ux + uy * uy + uz * uz));
+  const float qw = q * w * ig * scale;
+  amp[0] = qw * ux;
+  amp[1] = qw * uy;
+  amp[2] = qw * uz;
+}
+
 template <int O, int DIM>
 __device__ __forceinline__ void prep_shapes(PartPrep<O, DIM>& p) {
 #pragma unroll
