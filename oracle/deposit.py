@@ -169,6 +169,44 @@ def deposit(g, pos, u, w, valid=None):
     return J
 
 
+RHO = -1   # "component" of the charge density: nodal in every dimension
+
+
+def deposit_rho(g, pos, w, valid=None):
+    """Charge density, the scalar and nodal counterpart of Eq. 1 (the charge assignment of
+    Appendix B): rho(m) = sum_p q W_p prod_d B_o(m_d - xi_{p,d}). Shape g.shape."""
+    pos = _select(pos[: g.dim], valid)
+    w = _select([w], valid)[0].astype(np.float64)
+    xis, _ = grid_coords(g, pos)
+    amp = g.q * w
+    st = _stencils(g, xis, RHO)
+    acc = np.zeros(g.size, dtype=np.float64)
+    for ks in _combos(g):
+        val = amp.copy()
+        idx = []
+        for d in range(g.dim):
+            val = val * st[d][1][:, ks[d]]
+            idx.append(st[d][0][:, ks[d]])
+        acc += np.bincount(_flat(g, idx), weights=val, minlength=g.size)
+    return acc.reshape(g.shape)
+
+
+def deposit_rho_bruteforce(g, pos, w, valid=None):
+    """All nodes x all particles with the continuous kernel B_o (tiny inputs only)."""
+    pos = _select(pos[: g.dim], valid)
+    w = _select([w], valid)[0].astype(np.float64)
+    xis, _ = grid_coords(g, pos)
+    prod = None
+    for d in reversed(range(g.dim)):
+        nodes = np.arange(-g.guard(d), g.n[d] + g.guard(d)).astype(np.float64)
+        t = nodes[:, None] - xis[d][None, :]
+        if g.bc[d] == PERIODIC:
+            t = t - g.n[d] * np.round(t / g.n[d])
+        k = shapes.kernel(g.order, t)
+        prod = k if prod is None else (prod[:, None, :] * k[None, :, :]).reshape(-1, len(w))
+    return (prod @ (g.q * w)).reshape(g.shape)
+
+
 def deposit_add_at(g, pos, u, w, valid=None):
     """Same sum as deposit(), accumulated one particle and one node at a time.
 
