@@ -172,6 +172,7 @@ def main():
     }
     if not args.no_extras:
         out["paths"] = path_table(pic, torch, grid, parts, bins, N, ncell)
+        out["charge_density"] = rho_line(pic, torch, grid, parts, bins, N, ncell)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     bins.close()
     if args.calib_copy:
@@ -367,6 +368,29 @@ def path_table(pic, torch, grid, parts, bins, N, ncell):
             res[name] = {"error": str(exc)}
     s_bins.close()
     return res
+
+
+def rho_line(pic, torch, grid, parts, bins, N, ncell):
+    """pic_deposit_rho on the bench snapshot (order 3, nodal), with its rel-L2 against the
+    FP64 oracle on the 32^3 scaled copy."""
+    from paper_2601_08277_amd import synth
+    from oracle import deposit as od
+    from oracle.deposit import OracleGrid
+    rho = torch.empty(grid.shape, dtype=torch.float32, device=parts.x.device)
+    ms = _events_ms(torch, lambda: pic.deposit_rho(grid, parts, bins, 0, rho), 10)
+    sp, sa = synth.c2(n=(32, 32, 32))
+    sg = pic.Grid(sp)
+    s_slots = pic.slots_for(sa["x"].size, 32 ** 3, 0.25)
+    s_parts = pic.Particles.from_arrays(sa, s_slots)
+    s_bins = pic.Bins(sg, (8, 8, 4), 0.25, s_slots)
+    pic.rebin(sg, s_parts, s_bins, pic.REBIN_FULL)
+    got = pic.deposit_rho(sg, s_parts, s_bins).cpu().numpy()
+    want = od.deposit_rho(OracleGrid.from_params(sp), [sa["x"], sa["y"], sa["z"]], sa["w"])
+    s_bins.close()
+    byts = N * 32 + ncell * 4      # positions + weight in, one grid out
+    return {"particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
+            "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "rel_l2_vs_oracle_32cubed": float(np.linalg.norm(got - want) / np.linalg.norm(want))}
 
 
 def cpu_baseline(sample):

@@ -200,6 +200,16 @@ pic_status pic_deposit_backward(const pic_grid* grid, const pic_particles* p,
                                 float* dux, float* duy, float* duz, float* dw,
                                 unsigned flags, hipStream_t stream);
 
+/* Charge density rho(m) = sum_p q W_p prod_d B_o(m_d - xi_{p,d}): the scalar, nodal
+ * counterpart of pic_deposit (no velocity, no staggering in any dimension), i.e. the
+ * charge/mass assignment of the paper's Appendix B on the same sorted tiles. `rho` is one
+ * float32 grid in the layout of a J component (device, caller-owned); it is overwritten
+ * unless PIC_F_ACCUMULATE (the only flag accepted). Needs bins filled by pic_rebin.
+ * Errors: INVALID_ARG (bad arguments, other flags, no bins), UNSUPPORTED (tile window over
+ * the LDS limit); out-of-domain and non-finite positions are reported by pic_check. */
+pic_status pic_deposit_rho(const pic_grid* grid, const pic_particles* p, pic_bins* bins,
+                           float* rho, unsigned flags, hipStream_t stream);
+
 /* Constant-velocity move of every valid particle, x += v dt (float64), with periodic
  * wrap: the stand-in for the particle push between steps. */
 pic_status pic_drift(const pic_grid* grid, pic_particles* p, double dt, hipStream_t stream);

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "pic_host.h"
+#include "deposit_common.h"
 
 static thread_local std::string g_last_error;
 
@@ -439,6 +440,27 @@ extern "C" pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bi
     else if (flags & PIC_F_DRIFT) b->movers_fresh = false;
   }
   return check_hip(hipGetLastError(), "pic_deposit launch");
+}
+
+extern "C" pic_status pic_deposit_rho(const pic_grid* grid, const pic_particles* p, pic_bins* b,
+                                      float* rho, unsigned flags, hipStream_t stream) {
+  pic_status st = validate_grid(grid);
+  if (st != PIC_OK) return st;
+  if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
+  if (!rho) return set_error(PIC_ERR_INVALID_ARG, "rho must not be NULL");
+  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC))
+    return set_error(PIC_ERR_INVALID_ARG, "pic_deposit_rho takes PIC_F_ACCUMULATE only");
+  if (!b) return set_error(PIC_ERR_INVALID_ARG, "bins required");
+  if (!same_grid(*grid, b->grid)) return set_error(PIC_ERR_INVALID_ARG, "grid differs from the bins' grid");
+  if (p->nslots != b->nslots) return set_error(PIC_ERR_INVALID_ARG, "nslots differs from the bins' nslots");
+  if (!b->sorted_once) return set_error(PIC_ERR_INVALID_ARG, "bins are empty: run pic_rebin(PIC_REBIN_FULL) first");
+  KGrid G = make_kgrid(*grid);
+  KPart P = make_kpart(*p);
+  if (!(flags & PIC_F_ACCUMULATE)) launch_fill_f32(rho, (int64_t)G.N[0] * G.N[1] * G.N[2], 0.0f, stream);
+  if (!deposit_rho_cell_launch(G, P, b, rho, stream))
+    return set_error(PIC_ERR_UNSUPPORTED, "tile window too large for LDS");
+  halo_rho_launch(G, b, rho, stream);
+  return check_hip(hipGetLastError(), "pic_deposit_rho launch");
 }
 
 extern "C" pic_status pic_deposit_backward(const pic_grid* grid, const pic_particles* p,

@@ -178,11 +178,10 @@ __global__ __launch_bounds__(256) void k_dep_tile_atomic(KGrid G, KBins B, KPart
 // J += sum of the stored tile windows covering each node (at most 2 tiles per
 // dimension for tiles at least as wide as the stencil reach). One thread per node, all
 // three components.
-// J node idx (flat, stored layout) = sum over the tile windows that cover it.
+// Sums over the tile windows that cover node idx (flat, stored layout), per window copy.
 template <int O, int DIM>
-__device__ __forceinline__ void halo_node(const KGrid& G, const KBins& B, float* __restrict__ J0,
-                                          float* __restrict__ J1, float* __restrict__ J2,
-                                          int64_t idx) {
+__device__ __forceinline__ void halo_sums(const KGrid& G, const KBins& B, int64_t idx, float& s0,
+                                          float& s1, float& s2) {
   constexpr int LO = TileWin<O, DIM>::LO, R = TileWin<O, DIM>::R;
   const int n3[3] = {(int)(idx % G.N[0]), (int)((idx / G.N[0]) % G.N[1]),
                      (int)(idx / ((int64_t)G.N[0] * G.N[1]))};
@@ -204,7 +203,9 @@ __device__ __forceinline__ void halo_node(const KGrid& G, const KBins& B, float*
       cnt[d] = halo_cands(n3[d] - G.g[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d], cnt[d]);
     }
   }
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+  s0 = 0.f;
+  s1 = 0.f;
+  s2 = 0.f;
   for (int a = 0; a < cnt[2]; ++a)
     for (int b = 0; b < cnt[1]; ++b)
       for (int c = 0; c < cnt[0]; ++c) {
@@ -217,9 +218,42 @@ __device__ __forceinline__ void halo_node(const KGrid& G, const KBins& B, float*
         s1 += src[B.wmax];
         s2 += src[2 * B.wmax];
       }
+}
+
+// J node idx = sum over the tile windows that cover it.
+template <int O, int DIM>
+__device__ __forceinline__ void halo_node(const KGrid& G, const KBins& B, float* __restrict__ J0,
+                                          float* __restrict__ J1, float* __restrict__ J2,
+                                          int64_t idx) {
+  float s0, s1, s2;
+  halo_sums<O, DIM>(G, B, idx, s0, s1, s2);
   J0[idx] += s0;
   J1[idx] += s1;
   J2[idx] += s2;
+}
+
+// Charge density: the three window copies of each covering tile, summed.
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_halo_rho(KGrid G, KBins B, float* __restrict__ rho) {
+  const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride) {
+    float s0, s1, s2;
+    halo_sums<O, DIM>(G, B, idx, s0, s1, s2);
+    rho[idx] += (s0 + s1) + s2;
+  }
+}
+
+void halo_rho_launch(const KGrid& G, pic_bins* b, float* rho, hipStream_t s) {
+  const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 16384));
+#define HR(O_, D_) hipLaunchKernelGGL((k_halo_rho<O_, D_>), dim3(blocks), dim3(256), 0, s, G, b->kb, rho)
+  if (G.dim == 3) {
+    if (G.order == 1) HR(1, 3); else if (G.order == 2) HR(2, 3); else HR(3, 3);
+  } else {
+    if (G.order == 1) HR(1, 2); else if (G.order == 2) HR(2, 2); else HR(3, 2);
+  }
+#undef HR
 }
 
 template <int O, int DIM>

@@ -25,13 +25,15 @@
 // the extra node carries a zero weight.
 #include "deposit_common.h"
 
-template <int O, int DIM>
+// Window extent of accumulator set c along d: component c of J is staggered along its own
+// axis; the charge density (RHO) is nodal everywhere.
+template <int O, int DIM, bool RHO = false>
 __host__ __device__ constexpr int cwin(int c, int d) {
-  return d < DIM ? win_w(O, c == d) : 1;
+  return d < DIM ? win_w(O, !RHO && c == d) : 1;
 }
-template <int O, int DIM>
+template <int O, int DIM, bool RHO = false>
 __host__ __device__ constexpr int csz(int c) {
-  return cwin<O, DIM>(c, 0) * cwin<O, DIM>(c, 1) * cwin<O, DIM>(c, 2);
+  return cwin<O, DIM, RHO>(c, 0) * cwin<O, DIM, RHO>(c, 1) * cwin<O, DIM, RHO>(c, 2);
 }
 // Weights placed on the padded window: out[a] = w[a - s] (zero outside).
 template <int O, int W>
@@ -150,6 +152,36 @@ struct CvRaw {
   int s, lc, si;
 };
 
+// One particle's charge density through global atomics (the rare overflow of a tile's
+// stale list in the density mode).
+template <int O, int DIM>
+__device__ __forceinline__ void cv_rho_particle_global(const KGrid& G, const PartPrep<O, DIM>& p,
+                                                       float* rho, uint32_t& bad) {
+  float w[3][O + 1];
+  int base[3] = {0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d < DIM) {
+      base[d] = p.cell[d] + win_lo(O, false) + shape_w<O, false>(p.f[d], w[d]);
+    } else {
+#pragma unroll
+      for (int k = 0; k <= O; ++k) w[d][k] = k == 0 ? 1.0f : 0.0f;
+    }
+  }
+  for (int kz = 0; kz < (DIM == 3 ? O + 1 : 1); ++kz)
+    for (int ky = 0; ky <= O; ++ky)
+      for (int kx = 0; kx <= O; ++kx) {
+        const float v = p.amp[0] * w[0][kx] * w[1][ky] * w[2][kz];
+        const int ix = store_idx(G, 0, base[0] + kx), iy = store_idx(G, 1, base[1] + ky);
+        const int iz = DIM == 3 ? store_idx(G, 2, base[2] + kz) : 0;
+        if ((ix | iy | iz) < 0) {
+          if (v != 0.0f) bad |= PIC_EF_STENCIL;
+          continue;
+        }
+        unsafeAtomicAdd(&rho[((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
+      }
+}
+
 // w[i] by selects (the empty asm keeps the compiler from turning it into an indexed
 // load from a stack copy of w).
 template <int O>
@@ -183,7 +215,7 @@ __device__ __forceinline__ void cv_particle_global(const KGrid& G, PartPrep<O, D
 // Producer wave: stage the unit's particles (staged index in [R0, R0 + CV_CAP)) into one
 // stage buffer, lanes = slots (coalesced loads, the next chunk's loads in flight while the
 // current chunk is processed).
-template <int O, int DIM>
+template <int O, int DIM, bool RHO>
 __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const KPart& P,
                                          const TileBox& tb, const int32_t* s_off,
                                          const int32_t* s_len, const CellGroup& gr, float* sf,
@@ -237,7 +269,12 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
       bool ok = false, mine = false;
       if (r.lc >= 0) {
         ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad);
-        prep_amp_rsq(G.q, r.ux, r.uy, r.uz, r.w, 1.0f, p.amp);
+        if constexpr (RHO) {
+          p.amp[0] = G.q * r.w;       // charge density: q W, no velocity
+          p.amp[1] = p.amp[2] = 0.0f;
+        } else {
+          prep_amp_rsq(G.q, r.ux, r.uy, r.uz, r.w, 1.0f, p.amp);
+        }
         // the particle's cell relative to the tile -> local bin (no division)
         const int lx = p.cell[0] - tb.c0[0], ly = p.cell[1] - tb.c0[1];
         const int lz = DIM == 3 ? p.cell[2] - tb.c0[2] : 0;
@@ -264,6 +301,8 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
               q.f[d] = d < DIM ? p.f[d] : 0.0f;
               q.amp[d] = p.amp[d];
             }
+          } else if constexpr (RHO) {
+            cv_rho_particle_global<O, DIM>(G, p, J[0], bad);
           } else {
             cv_particle_global<O, DIM>(G, p, J, bad);
           }
@@ -288,29 +327,34 @@ __device__ __forceinline__ int cv_shape(float f, float* w) {
   else return shape_w<O, STAG>(f, w);
 }
 
-// Accumulate component C of the lane's cell from the staged particles [k0, k1).
-template <int O, int DIM, int C>
+// Accumulate set C of the lane's cell from the staged particles [k0, k1): component C of J,
+// or (RHO) every third particle starting at the C-th for the charge density, so the three
+// waves share the particles of a cell and each fills its own copy of the window.
+template <int O, int DIM, int C, bool RHO>
 __device__ __forceinline__ void cv_accumulate(int k0, int k1, const float* sf, const float* sa,
                                               float* acc) {
-  constexpr int WX = cwin<O, DIM>(C, 0), WY = cwin<O, DIM>(C, 1), WZ = cwin<O, DIM>(C, 2);
-  const int n = k1 - k0;
+  constexpr int WX = cwin<O, DIM, RHO>(C, 0), WY = cwin<O, DIM, RHO>(C, 1),
+                WZ = cwin<O, DIM, RHO>(C, 2);
+  constexpr int STEP = RHO ? 3 : 1;
+  const int first = RHO ? k0 + C : k0;
+  const int n = k1 > first ? (k1 - first + STEP - 1) / STEP : 0;
   const int nmax = wave_max(n);
   for (int k = 0; k < nmax; ++k) {
     const bool act = k < n;
-    const int q = act ? k0 + k : 0;
+    const int q = act ? first + k * STEP : 0;
     float f[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) f[d] = sf[d * CV_CAP + q];
-    const float amp = act ? sa[C * CV_CAP + q] : 0.0f;
+    const float amp = act ? sa[(RHO ? 0 : C) * CV_CAP + q] : 0.0f;
     float wx[5], wy[5], wz[5];
     {
       float w[O + 1];
-      int sh = cv_shape<O, C == 0>(f[0], w);
+      int sh = cv_shape<O, !RHO && C == 0>(f[0], w);
       pad_w<O, WX>(w, sh, wx);
-      sh = cv_shape<O, C == 1>(f[1], w);
+      sh = cv_shape<O, !RHO && C == 1>(f[1], w);
       pad_w<O, WY>(w, sh, wy);
       if constexpr (DIM == 3) {
-        sh = cv_shape<O, C == 2>(f[2], w);
+        sh = cv_shape<O, !RHO && C == 2>(f[2], w);
         pad_w<O, WZ>(w, sh, wz);
       } else {
         wz[0] = 1.0f;
@@ -337,13 +381,14 @@ __device__ __forceinline__ void cv_accumulate(int k0, int k1, const float* sf, c
 // barrier keeps each read behind the previous write. When all cells of the group lie in
 // one z-plane, two lanes can only meet on a node through offsets that differ in x or y, so
 // the z-column of one (ix, iy) offset is read, added and written as a batch.
-template <int O, int DIM, int C, bool ZBATCH>
+template <int O, int DIM, int C, bool ZBATCH, bool RHO>
 __device__ __forceinline__ void cv_flush(const TileWin<O, DIM>& tw, const int* cc,
                                          const float* acc, float* win, bool own) {
-  constexpr int WX = cwin<O, DIM>(C, 0), WY = cwin<O, DIM>(C, 1), WZ = cwin<O, DIM>(C, 2);
-  const int lx = cc[0] + win_lo(O, C == 0);
-  const int ly = cc[1] + win_lo(O, C == 1);
-  const int lz = DIM == 3 ? cc[2] + win_lo(O, C == 2) : 0;
+  constexpr int WX = cwin<O, DIM, RHO>(C, 0), WY = cwin<O, DIM, RHO>(C, 1),
+                WZ = cwin<O, DIM, RHO>(C, 2);
+  const int lx = cc[0] + win_lo(O, !RHO && C == 0);
+  const int ly = cc[1] + win_lo(O, !RHO && C == 1);
+  const int lz = DIM == 3 ? cc[2] + win_lo(O, !RHO && C == 2) : 0;
 #pragma unroll
   for (int iy = 0; iy < WY; ++iy)
 #pragma unroll
@@ -371,20 +416,22 @@ __device__ __forceinline__ void cv_flush(const TileWin<O, DIM>& tw, const int* c
     }
 }
 
-template <int O, int DIM>
+template <int O, int DIM, bool RHO = false>
 __host__ __device__ constexpr int csz_max() {
-  return csz<O, DIM>(0) > csz<O, DIM>(1) ? (csz<O, DIM>(0) > csz<O, DIM>(2) ? csz<O, DIM>(0) : csz<O, DIM>(2))
-                                         : (csz<O, DIM>(1) > csz<O, DIM>(2) ? csz<O, DIM>(1) : csz<O, DIM>(2));
+  return csz<O, DIM, RHO>(0) > csz<O, DIM, RHO>(1)
+             ? (csz<O, DIM, RHO>(0) > csz<O, DIM, RHO>(2) ? csz<O, DIM, RHO>(0) : csz<O, DIM, RHO>(2))
+             : (csz<O, DIM, RHO>(1) > csz<O, DIM, RHO>(2) ? csz<O, DIM, RHO>(1) : csz<O, DIM, RHO>(2));
 }
 
 
 // End phase, wave C: component C of every stale particle of the tile, one particle at a
 // time with lanes = stencil nodes (distinct nodes, so plain read-add-write into the tile
 // window; nodes outside the window go to J with global atomics).
-template <int O, int DIM, int C>
+template <int O, int DIM, int C, bool RHO>
 __device__ __forceinline__ void cv_stale(const KGrid& G, const TileWin<O, DIM>& tw,
                                          const StaleRec* stale, int nstale, float* win,
                                          float* const* J, uint32_t& bad) {
+  if constexpr (RHO && C != 0) return;      // the density has one set: wave 0 adds it
   constexpr int NS = (O + 1) * (O + 1) * (DIM == 3 ? O + 1 : 1);
   const int lane = threadIdx.x % PIC_WAVE;
   for (int e = 0; e < nstale; ++e) {
@@ -394,9 +441,9 @@ __device__ __forceinline__ void cv_stale(const KGrid& G, const TileWin<O, DIM>& 
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
       int sh;
-      if (d == C) sh = shape_w<O, true>(q.f[d], w[d]);
+      if (!RHO && d == C) sh = shape_w<O, true>(q.f[d], w[d]);
       else sh = shape_w<O, false>(q.f[d], w[d]);
-      base[d] = q.cell[d] + win_lo(O, d == C) + sh;
+      base[d] = q.cell[d] + win_lo(O, !RHO && d == C) + sh;
     }
     for (int j = lane; j < NS; j += PIC_WAVE) {
       const int ix = j % (O + 1), iy = (j / (O + 1)) % (O + 1), iz = j / ((O + 1) * (O + 1));
@@ -424,7 +471,7 @@ __device__ __forceinline__ void cv_stale(const KGrid& G, const TileWin<O, DIM>& 
 }
 
 // Consumer wave C: flush component C of the group's cells into the tile window.
-template <int O, int DIM, int C>
+template <int O, int DIM, int C, bool RHO>
 __device__ __forceinline__ void cv_flush_group(const TileBox& tb, const TileWin<O, DIM>& tw,
                                                const CellGroup& gr, const float* acc,
                                                float* win) {
@@ -440,8 +487,8 @@ __device__ __forceinline__ void cv_flush_group(const TileBox& tb, const TileWin<
   for (int d = 0; d < 3; ++d) cc[d] += tb.c0[d];
   const bool plane = DIM == 3 && (gr.g0 / exy) == ((gr.g0 + gr.gn - 1) / exy);
   const bool o = own && gr.n > 0;
-  if (plane) cv_flush<O, DIM, C, true>(tw, cc, acc, win, o);
-  else cv_flush<O, DIM, C, false>(tw, cc, acc, win, o);
+  if (plane) cv_flush<O, DIM, C, true, RHO>(tw, cc, acc, win, o);
+  else cv_flush<O, DIM, C, false, RHO>(tw, cc, acc, win, o);
 }
 
 // Consumer wave c, after accumulating a unit: the fused drift (x += v dt, FP64) and mover
@@ -505,27 +552,27 @@ __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, co
   }
 }
 
-template <int O, int DIM, int C>
+template <int O, int DIM, int C, bool RHO>
 __device__ __forceinline__ void cv_consume(int k0, int k1, const float* sf, const float* sa,
                                            float* acc, bool last, const TileBox& tb,
                                            const TileWin<O, DIM>& tw, const CellGroup& gr,
                                            float* win) {
-  cv_accumulate<O, DIM, C>(k0, k1, sf, sa, acc);
+  cv_accumulate<O, DIM, C, RHO>(k0, k1, sf, sa, acc);
   if (last) {
-    cv_flush_group<O, DIM, C>(tb, tw, gr, acc, win);
+    cv_flush_group<O, DIM, C, RHO>(tb, tw, gr, acc, win);
 #pragma unroll
-    for (int i = 0; i < csz_max<O, DIM>(); ++i) acc[i] = 0.0f;
+    for (int i = 0; i < csz_max<O, DIM, RHO>(); ++i) acc[i] = 0.0f;
   }
 }
 
 // One workgroup per tile: the producer wave(s) stage unit u + 1 while waves 0..2 accumulate
 // unit u. Every wave walks the same units and passes the same number of barriers. (A
 // workgroup of more than four waves was measured to fit only once per CU.)
-template <int O, int DIM>
+template <int O, int DIM, bool RHO = false>
 __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const KPart& P,
                                           float* J0, float* J1, float* J2, unsigned flags,
                                           double dt, int tile, unsigned char* smem_raw) {
-  constexpr int NA = csz_max<O, DIM>();
+  constexpr int NA = csz_max<O, DIM, RHO>();
   const CellLayout<O, DIM> L(B);
   const TileBox tb = tile_box(G.n, B.T, B.nt, tile);
   const TileWin<O, DIM> tw(tb);
@@ -555,7 +602,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   // accumulators are not live across the producer's code.
   if (producer) {
     if (cur.g0 < tb.nb)
-      cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, map_p, stale,
+      cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, map_p, stale,
                        s_nstale, J, bad);
     __syncthreads();
     int ub = 0;
@@ -563,7 +610,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
       const CellGroup nxt = cv_next_unit(cur, s_off, s_len, tb.nb, lane);
       if (nxt.g0 < tb.nb) {
         float* nf = stage + (ub ^ 1) * 6 * CV_CAP;
-        cv_stage<O, DIM>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, map_p, stale,
+        cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, map_p, stale,
                          s_nstale, J, bad);
       }
       __syncthreads();
@@ -582,23 +629,23 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
       const int k0 = min(max(cur.st, cur.R0), cur.R0 + CV_CAP) - cur.R0;
       const int k1 = min(max(cur.st + cur.n, cur.R0), cur.R0 + CV_CAP) - cur.R0;
       const bool last = cur.R0 + CV_CAP >= cur.ntot;
-      if (wave == 0) cv_consume<O, DIM, 0>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
-      else if (wave == 1) cv_consume<O, DIM, 1>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
-      else cv_consume<O, DIM, 2>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
-      if (flags & (PIC_F_DRIFT | PIC_F_EMIT_MOVERS))
+      if (wave == 0) cv_consume<O, DIM, 0, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
+      else if (wave == 1) cv_consume<O, DIM, 1, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
+      else cv_consume<O, DIM, 2, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
+      if (!RHO && (flags & (PIC_F_DRIFT | PIC_F_EMIT_MOVERS)))
         cv_drift_unit<DIM>(G, B, P, tb, s_off, s_len, cur, wave, mb, flags, dt, bad);
       __syncthreads();
       cur = nxt;
       ub ^= 1;
     }
-    if (flags & PIC_F_EMIT_MOVERS) mb_flush(mb, B);
+    if (!RHO && (flags & PIC_F_EMIT_MOVERS)) mb_flush(mb, B);
   }
   __syncthreads();
   const int ns = min(*s_nstale, CV_STALE);
   if (ns > 0) {
-    if (wave == 0) cv_stale<O, DIM, 0>(G, tw, stale, ns, win, J, bad);
-    else if (wave == 1) cv_stale<O, DIM, 1>(G, tw, stale, ns, win, J, bad);
-    else if (wave == 2) cv_stale<O, DIM, 2>(G, tw, stale, ns, win, J, bad);
+    if (wave == 0) cv_stale<O, DIM, 0, RHO>(G, tw, stale, ns, win, J, bad);
+    else if (wave == 1) cv_stale<O, DIM, 1, RHO>(G, tw, stale, ns, win, J, bad);
+    else if (wave == 2) cv_stale<O, DIM, 2, RHO>(G, tw, stale, ns, win, J, bad);
   }
   if (bad) atomicOr(B.err, bad);
   __syncthreads();
@@ -611,6 +658,16 @@ __global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 3) void k_dep_cell_valu(
     float* __restrict__ J2, unsigned flags, double dt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cell_tile<O, DIM>(G, B, P, J0, J1, J2, flags, dt, blockIdx.x, smem_raw);
+}
+
+// Charge density on the same tiles: the three component waves take every third particle of
+// each cell into three copies of the window (summed by the density window sum).
+template <int O, int DIM>
+__global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 3) void k_dep_cell_rho(KGrid G, KBins B,
+                                                                         KPart P,
+                                                                         float* __restrict__ rho) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cell_tile<O, DIM, true>(G, B, P, rho, rho, rho, 0u, 0.0, blockIdx.x, smem_raw);
 }
 
 // Persistent batched deposition (3D patches, any order): each workgroup pulls (patch,
@@ -675,6 +732,27 @@ void batched_cell_launch(const BatchPatch* pd, const int2* items, int nitems, in
                          int blocks, size_t smem, unsigned flags, hipStream_t s) {
   hipLaunchKernelGGL(k_dep_cell_batched, dim3(blocks), dim3(CV_WAVES * PIC_WAVE), smem, s, pd,
                      items, nitems, queue, flags);
+}
+
+template <int O, int DIM>
+static bool launch_cell_rho(const KGrid& G, const KPart& P, pic_bins* b, float* rho,
+                            hipStream_t s) {
+  const size_t smem = CellLayout<O, DIM>(b->kb).total;
+  if (smem > b->max_lds) return false;
+  hipLaunchKernelGGL((k_dep_cell_rho<O, DIM>), dim3(b->kb.ntiles), dim3(CV_WAVES * PIC_WAVE), smem,
+                     s, G, b->kb, P, rho);
+  return true;
+}
+
+bool deposit_rho_cell_launch(const KGrid& G, const KPart& P, pic_bins* b, float* rho,
+                             hipStream_t s) {
+#define CR(O_, D_) return launch_cell_rho<O_, D_>(G, P, b, rho, s)
+  if (G.dim == 3) {
+    if (G.order == 1) CR(1, 3); else if (G.order == 2) CR(2, 3); else CR(3, 3);
+  } else {
+    if (G.order == 1) CR(1, 2); else if (G.order == 2) CR(2, 2); else CR(3, 2);
+  }
+#undef CR
 }
 
 int choose_path(const KGrid& G, const pic_bins* b) {

@@ -218,6 +218,11 @@ void batched_prologue_launch(const BatchPatch* pd, int npatch, int64_t max_nodes
                              unsigned flags, hipStream_t s);
 void batched_halo_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, hipStream_t s);
 
+// Charge density on the per-cell path (deposit_cell.hip) and its window sum (deposit.hip).
+bool deposit_rho_cell_launch(const KGrid& G, const KPart& P, pic_bins* b, float* rho,
+                             hipStream_t s);
+void halo_rho_launch(const KGrid& G, pic_bins* b, float* rho, hipStream_t s);
+
 // Path selection and the per-cell paths (deposit_cell.hip).
 int choose_path(const KGrid& G, const pic_bins* b);
 bool deposit_cell_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, float* J1,

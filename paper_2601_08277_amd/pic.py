@@ -24,7 +24,8 @@ INVALID_ID = -1
 
 EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "pic_bins_destroy",
            "pic_bins_get_view", "pic_bins_copy_tables", "pic_rebin", "pic_rebin_stats_read", "pic_bins_report_perf",
-           "pic_deposit", "pic_deposit_backward", "pic_drift", "pic_plan_create",
+           "pic_deposit", "pic_deposit_rho", "pic_deposit_backward", "pic_drift",
+           "pic_plan_create",
            "pic_plan_destroy", "pic_deposit_batched", "pic_plan_info", "pic_check",
            "pic_last_error"]
 
@@ -326,6 +327,16 @@ def deposit_batched(plan, parts_list, J_list=None, path=PATH_AUTO, flags=0):
     jarr = (ctypes.c_void_p * (3 * n))(*[J[c].data_ptr() for J in J_list for c in range(3)])
     _check(lib().pic_deposit_batched(plan.h, parr, jarr, path, flags, _stream()))
     return J_list
+
+
+def deposit_rho(grid, parts, bins, flags=0, rho=None):
+    """Charge density on the grid (pic_deposit_rho); returns the rho tensor."""
+    if rho is None:
+        rho = torch.empty(grid.shape, dtype=torch.float32, device=parts.x.device)
+    pc = parts.c()
+    _check(lib().pic_deposit_rho(ctypes.byref(grid.c), ctypes.byref(pc), bins.h, _ptr(rho),
+                                 flags, _stream()))
+    return rho
 
 
 def deposit_backward(grid, parts, bins, G, want_dw=True):
