@@ -316,6 +316,68 @@ def deposit_adjoint(g, pos, u, w, G, valid=None):
     return out
 
 
+def stagger_b(g, comp, d):
+    """Magnetic component c sits half a cell along the two other axes (Yee faces)."""
+    return 0.5 if (d != comp and d < g.dim) else 0.0
+
+
+def _stencils_sigma(g, xis, sig):
+    """Like _stencils for an explicit per-dimension shift sig[d] in {0, 1/2}."""
+    out = []
+    for d in range(g.dim):
+        base, W = shapes.weights(g.order, xis[d] - sig[d])
+        m = base[:, None] + np.arange(g.order + 1)[None, :]
+        out.append((_node_index(g, d, m, W), W))
+    return out
+
+
+def _gather_one(g, F, xis, sig):
+    Ff = np.asarray(F, dtype=np.float64).reshape(-1)
+    st = _stencils_sigma(g, xis, sig)
+    acc = np.zeros(len(xis[0]))
+    for ks in _combos(g):
+        idx = [st[d][0][:, ks[d]] for d in range(g.dim)]
+        val = Ff[_flat(g, idx)]
+        for d in range(g.dim):
+            val = val * st[d][1][:, ks[d]]
+        acc += val
+    return acc
+
+
+def gather_fields(g, pos, E, B, valid=None):
+    """Field interpolation to the particles (the gather of Sec. 3.1, the forward of the
+    adjoint's gather): E_c(x_p) = sum_m E_c(m) prod_d B_o(m_d + sigma^E_{c,d} - xi_{p,d}),
+    likewise B_c with sigma^B. E_c sits on its own axis' edge (as J_c), B_c on the face
+    normal to c (half a cell along the two other axes). Returns ([Ex, Ey, Ez], [Bx, By, Bz])
+    per particle."""
+    pos = _select(pos[: g.dim], valid)
+    xis, _ = grid_coords(g, pos)
+    Ep = [_gather_one(g, E[c], xis, [stagger(g, c, d) for d in range(g.dim)]) for c in range(3)]
+    Bp = [_gather_one(g, B[c], xis, [stagger_b(g, c, d) for d in range(g.dim)]) for c in range(3)]
+    return Ep, Bp
+
+
+def gather_fields_bruteforce(g, pos, E, B, valid=None):
+    """All nodes x all particles with the continuous kernel B_o (tiny inputs only)."""
+    pos = _select(pos[: g.dim], valid)
+    xis, _ = grid_coords(g, pos)
+
+    def one(F, sig):
+        prod = None
+        for d in reversed(range(g.dim)):
+            nodes = np.arange(-g.guard(d), g.n[d] + g.guard(d)).astype(np.float64)
+            t = nodes[:, None] + sig[d] - xis[d][None, :]
+            if g.bc[d] == PERIODIC:
+                t = t - g.n[d] * np.round(t / g.n[d])
+            k = shapes.kernel(g.order, t)
+            prod = k if prod is None else (prod[:, None, :] * k[None, :, :]).reshape(-1, len(xis[0]))
+        return np.asarray(F, dtype=np.float64).reshape(-1) @ prod
+
+    Ep = [one(E[c], [stagger(g, c, d) for d in range(g.dim)]) for c in range(3)]
+    Bp = [one(B[c], [stagger_b(g, c, d) for d in range(g.dim)]) for c in range(3)]
+    return Ep, Bp
+
+
 def drift(g, pos, u, dt):
     """Constant-velocity move x <- x + v dt between steps (float64), periodic wrap.
 
