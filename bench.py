@@ -173,6 +173,7 @@ def main():
     if not args.no_extras:
         out["paths"] = path_table(pic, torch, grid, parts, bins, N, ncell)
         out["charge_density"] = rho_line(pic, torch, grid, parts, bins, N, ncell)
+        out["field_gather"] = gather_line(pic, torch, grid, parts, bins, N, ncell)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     bins.close()
     if args.calib_copy:
@@ -391,6 +392,39 @@ def rho_line(pic, torch, grid, parts, bins, N, ncell):
     return {"particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
             "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "rel_l2_vs_oracle_32cubed": float(np.linalg.norm(got - want) / np.linalg.norm(want))}
+
+
+def gather_line(pic, torch, grid, parts, bins, N, ncell):
+    """pic_gather_fields (E, B to the particles, order 3) on the bench snapshot, with its
+    rel-L2 against the FP64 oracle on the 32^3 scaled copy."""
+    from paper_2601_08277_amd import synth
+    from oracle import deposit as od
+    from oracle.deposit import OracleGrid
+    g = torch.Generator(device="cuda").manual_seed(11)
+    F = [torch.randn(grid.shape, generator=g, device="cuda") for _ in range(6)]
+    ms = _events_ms(torch, lambda: pic.gather_fields(grid, parts, bins, F[:3], F[3:]), 10)
+    sp, sa = synth.c2(n=(32, 32, 32))
+    sg = pic.Grid(sp)
+    s_slots = pic.slots_for(sa["x"].size, 32 ** 3, 0.25)
+    s_parts = pic.Particles.from_arrays(sa, s_slots)
+    s_bins = pic.Bins(sg, (8, 8, 4), 0.25, s_slots)
+    pic.rebin(sg, s_parts, s_bins, pic.REBIN_FULL)
+    rng = np.random.default_rng(12)
+    Fs = [rng.normal(size=sg.shape).astype(np.float32) for _ in range(6)]
+    Ep, Bp = pic.gather_fields(sg, s_parts, s_bins, [torch.from_numpy(f).cuda() for f in Fs[:3]],
+                               [torch.from_numpy(f).cuda() for f in Fs[3:]])
+    ids = s_parts.id.cpu().numpy()
+    valid = ids != -1
+    order = np.argsort(ids[valid])
+    wE, wB = od.gather_fields(OracleGrid.from_params(sp), [sa["x"], sa["y"], sa["z"]],
+                              [f.astype(np.float64) for f in Fs[:3]],
+                              [f.astype(np.float64) for f in Fs[3:]])
+    err = max(float(np.linalg.norm(a.cpu().numpy()[valid][order] - b) / np.linalg.norm(b))
+              for a, b in zip(Ep + Bp, wE + wB))
+    s_bins.close()
+    byts = N * (24 + 24) + 6 * ncell * 4     # positions in, six values out, six grids in
+    return {"particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
+            "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "rel_l2_vs_oracle_32cubed": err}
 
 
 def cpu_baseline(sample):

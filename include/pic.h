@@ -210,6 +210,21 @@ pic_status pic_deposit_backward(const pic_grid* grid, const pic_particles* p,
 pic_status pic_deposit_rho(const pic_grid* grid, const pic_particles* p, pic_bins* bins,
                            float* rho, unsigned flags, hipStream_t stream);
 
+/* Field gather: E and B interpolated to every particle with the deposition's shape
+ * factors (field interpolation, Sec. 3.1). E_c is staggered half a cell along its own axis
+ * (the J_c location), B_c half a cell along the two other axes (Yee faces); in 2D, Ez is
+ * nodal and Bz is staggered in x and y. Fields: six float32 grids in the J layout (device,
+ * read only). Outputs: six float32 arrays of nslots (device, caller-owned), 0 on gap
+ * slots. With bins (filled by pic_rebin) each tile's window of the fields is read once into
+ * LDS; without bins the gather reads global memory per particle. Errors: INVALID_ARG (bad
+ * arguments, bins for another grid); stencil nodes outside the stored grid and
+ * out-of-domain positions are reported by pic_check. */
+pic_status pic_gather_fields(const pic_grid* grid, const pic_particles* p, pic_bins* bins,
+                             const float* Ex, const float* Ey, const float* Ez,
+                             const float* Bx, const float* By, const float* Bz, float* ex,
+                             float* ey, float* ez, float* bx, float* by, float* bz,
+                             hipStream_t stream);
+
 /* Constant-velocity move of every valid particle, x += v dt (float64), with periodic
  * wrap: the stand-in for the particle push between steps. */
 pic_status pic_drift(const pic_grid* grid, pic_particles* p, double dt, hipStream_t stream);

@@ -1,0 +1,206 @@
+// Field gather: E and B interpolated to the particles with the deposition's shape factors
+// (the field-interpolation half of the PIC cycle, Sec. 3.1; the forward of the adjoint's
+// gather). E_c sits on the edge along its own axis (as J_c); B_c on the face normal to c,
+// half a cell along the two other axes.
+//
+// Tiled like the adjoint: one workgroup per particle tile loads the tile's stencil window
+// of all six components into LDS, then its particles gather from LDS. Particles whose cell
+// is outside their tile are listed and gathered from global memory by k_gather_list.
+#include <algorithm>
+
+#include "deposit_common.h"
+
+uint32_t* nobins_err_ptr();
+
+// sum over the stencil of F at the particle, with per-dimension staggering SX, SY, SZ.
+template <int O, int DIM, bool SX, bool SY, bool SZ, class Fetch>
+__device__ __forceinline__ float gather_one(const int* cell, const float* f, int c,
+                                            Fetch&& fetch) {
+  float wx[O + 1], wy[O + 1], wz[O + 1];
+  const int bx = cell[0] + win_lo(O, SX) + shape_w<O, SX>(f[0], wx);
+  const int by = cell[1] + win_lo(O, SY) + shape_w<O, SY>(f[1], wy);
+  int bz = 0;
+  if constexpr (DIM == 3) {
+    bz = cell[2] + win_lo(O, SZ) + shape_w<O, SZ>(f[2], wz);
+  } else {
+#pragma unroll
+    for (int k = 0; k <= O; ++k) wz[k] = k == 0 ? 1.0f : 0.0f;
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int kz = 0; kz < (DIM == 3 ? O + 1 : 1); ++kz) {
+#pragma unroll
+    for (int ky = 0; ky <= O; ++ky) {
+      float sx = 0.0f;
+#pragma unroll
+      for (int kx = 0; kx <= O; ++kx)
+        sx += wx[kx] * fetch(c, bx + kx, by + ky, bz + kz, wx[kx] * wy[ky] * wz[kz]);
+      acc += wz[kz] * wy[ky] * sx;
+    }
+  }
+  return acc;
+}
+
+// The six gathered components of one particle; out[0..2] = E, out[3..5] = B.
+template <int O, int DIM, class Fetch>
+__device__ __forceinline__ void gather_particle(const int* cell, const float* f, Fetch&& fetch,
+                                                float* out) {
+  constexpr bool Z3 = DIM == 3;
+  out[0] = gather_one<O, DIM, true, false, false>(cell, f, 0, fetch);
+  out[1] = gather_one<O, DIM, false, true, false>(cell, f, 1, fetch);
+  out[2] = gather_one<O, DIM, false, false, Z3>(cell, f, 2, fetch);
+  out[3] = gather_one<O, DIM, false, true, Z3>(cell, f, 3, fetch);
+  out[4] = gather_one<O, DIM, true, false, Z3>(cell, f, 4, fetch);
+  out[5] = gather_one<O, DIM, true, true, false>(cell, f, 5, fetch);
+}
+
+struct GatherOut {
+  float* p[6];
+};
+
+struct FieldFetch {
+  const KGrid& G;
+  const float* const* F;
+  uint32_t& bad;
+  __device__ __forceinline__ float operator()(int c, int mx, int my, int mz, float w) const {
+    const int ix = store_idx(G, 0, mx), iy = store_idx(G, 1, my);
+    const int iz = G.dim == 3 ? store_idx(G, 2, mz) : 0;
+    if ((ix | iy | iz) >= 0) return F[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix];
+    if (w != 0.f) bad |= PIC_EF_STENCIL;
+    return 0.f;
+  }
+};
+
+struct FieldPtrs {
+  const float* f[6];
+};
+
+__device__ __forceinline__ void gather_write(const GatherOut& o, int s, const float* v) {
+#pragma unroll
+  for (int c = 0; c < 6; ++c) o.p[c][s] = v[c];
+}
+
+// Particle-parallel gather from global memory (no bins).
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_gather(KGrid G, KPart P, FieldPtrs F, GatherOut o,
+                                                uint32_t* err) {
+  uint32_t bad = 0;
+  const FieldFetch ff{G, F.f, bad};
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.nslots; s += gridDim.x * blockDim.x) {
+    int cell[3];
+    float f[3];
+    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (P.id[s] != PIC_INVALID_ID &&
+        prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad))
+      gather_particle<O, DIM>(cell, f, ff, v);
+    gather_write(o, s, v);
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_gather_tile(KGrid G, KBins B, KPart P, FieldPtrs F,
+                                                     GatherOut o, int32_t* __restrict__ list) {
+  extern __shared__ __align__(16) float sF[];
+  uint32_t bad = 0;
+  if (blockIdx.x == (unsigned)B.ntiles) {
+    const float z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int s = B.off[B.nbins] + threadIdx.x; s < P.nslots; s += blockDim.x) gather_write(o, s, z);
+    return;
+  }
+  const TileBox tb = tile_box(G.n, B.T, B.nt, blockIdx.x);
+  const TileWin<O, DIM> tw(tb);
+  for (int i = threadIdx.x; i < 6 * tw.size; i += blockDim.x) {
+    const int c = i / tw.size;
+    const int r = i - c * tw.size;
+    const int W01 = tw.W[0] * tw.W[1];
+    const int wz = r / W01, wy = (r - wz * W01) / tw.W[0], wx = r - wz * W01 - wy * tw.W[0];
+    const int ix = store_idx(G, 0, tw.o[0] + wx), iy = store_idx(G, 1, tw.o[1] + wy);
+    const int iz = DIM == 3 ? store_idx(G, 2, tw.o[2] + wz) : 0;
+    sF[i] = (ix | iy | iz) >= 0 ? F.f[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix] : 0.f;
+  }
+  __syncthreads();
+  auto lf = [&](int c, int mx, int my, int mz, float) -> float {
+    return sF[c * tw.size + ((mz - tw.o[2]) * tw.W[1] + (my - tw.o[1])) * tw.W[0] + (mx - tw.o[0])];
+  };
+  const int S0 = B.off[tb.b0], S1 = B.off[tb.b0 + tb.nb];
+  for (int base = S0; base < S1; base += blockDim.x) {
+    const int s = base + threadIdx.x;
+    int cell[3];
+    float f[3];
+    const bool ok = s < S1 && P.id[s] != PIC_INVALID_ID &&
+                    prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad);
+    const bool local = ok && tw.fits_cell(cell);
+    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (local) gather_particle<O, DIM>(cell, f, lf, v);
+    if (s < S1 && (local || !ok)) gather_write(o, s, v);
+    const int e = wave_append(ok && !local, &B.ctr[CTR_TOTAL]);
+    if (e >= 0) list[e] = s;
+  }
+  if (bad) atomicOr(B.err, bad);
+}
+
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_gather_list(KGrid G, KBins B, KPart P, FieldPtrs F,
+                                                     GatherOut o,
+                                                     const int32_t* __restrict__ list) {
+  uint32_t bad = 0;
+  const FieldFetch ff{G, F.f, bad};
+  const int n = B.ctr[CTR_TOTAL];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int s = list[e];
+    int cell[3];
+    float f[3];
+    float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad))
+      gather_particle<O, DIM>(cell, f, ff, v);
+    gather_write(o, s, v);
+  }
+  if (bad) atomicOr(B.err, bad);
+}
+
+template <int O, int DIM>
+static void launch_gather(const KGrid& G, const KPart& P, pic_bins* b, const FieldPtrs& F,
+                          const GatherOut& o, hipStream_t s) {
+  const size_t smem = b ? 6 * sizeof(float) * (size_t)TileWin<O, DIM>::max_size(b->kb) : 0;
+  if (b && b->sorted_once && smem <= b->max_lds) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->kb.ctr + CTR_TOTAL, (int64_t)1);
+    hipLaunchKernelGGL((k_gather_tile<O, DIM>), dim3(b->kb.ntiles + 1), dim3(256), smem, s, G,
+                       b->kb, P, F, o, b->sbin);
+    hipLaunchKernelGGL((k_gather_list<O, DIM>), dim3(256), dim3(256), 0, s, G, b->kb, P, F, o,
+                       b->sbin);
+    return;
+  }
+  const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)P.nslots + 255) / 256, 16384);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_gather<O, DIM>), dim3(blocks), dim3(256), 0, s, G, P, F, o,
+                     b ? b->kb.err : nobins_err_ptr());
+}
+
+extern "C" pic_status pic_gather_fields(const pic_grid* grid, const pic_particles* p,
+                                        pic_bins* b, const float* Ex, const float* Ey,
+                                        const float* Ez, const float* Bx, const float* By,
+                                        const float* Bz, float* ex, float* ey, float* ez,
+                                        float* bx, float* by, float* bz, hipStream_t stream) {
+  pic_status st = validate_grid(grid);
+  if (st != PIC_OK) return st;
+  if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
+  if (!Ex || !Ey || !Ez || !Bx || !By || !Bz || !ex || !ey || !ez || !bx || !by || !bz)
+    return set_error(PIC_ERR_INVALID_ARG, "field and output pointers must not be NULL");
+  if (b) {
+    if (!same_grid(*grid, b->grid)) return set_error(PIC_ERR_INVALID_ARG, "grid differs from the bins' grid");
+    if (p->nslots != b->nslots) return set_error(PIC_ERR_INVALID_ARG, "nslots differs from the bins' nslots");
+  }
+  const KGrid G = make_kgrid(*grid);
+  const KPart P = make_kpart(*p);
+  const FieldPtrs F{{Ex, Ey, Ez, Bx, By, Bz}};
+  const GatherOut o{{ex, ey, ez, bx, by, bz}};
+#define GA(O_, D_) launch_gather<O_, D_>(G, P, b, F, o, stream)
+  if (G.dim == 3) {
+    if (G.order == 1) GA(1, 3); else if (G.order == 2) GA(2, 3); else GA(3, 3);
+  } else {
+    if (G.order == 1) GA(1, 2); else if (G.order == 2) GA(2, 2); else GA(3, 2);
+  }
+#undef GA
+  return check_hip(hipGetLastError(), "pic_gather_fields launch");
+}

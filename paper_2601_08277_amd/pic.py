@@ -24,7 +24,8 @@ INVALID_ID = -1
 
 EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "pic_bins_destroy",
            "pic_bins_get_view", "pic_bins_copy_tables", "pic_rebin", "pic_rebin_stats_read", "pic_bins_report_perf",
-           "pic_deposit", "pic_deposit_rho", "pic_deposit_backward", "pic_drift",
+           "pic_deposit", "pic_deposit_rho", "pic_gather_fields", "pic_deposit_backward",
+           "pic_drift",
            "pic_plan_create",
            "pic_plan_destroy", "pic_deposit_batched", "pic_plan_info", "pic_check",
            "pic_last_error"]
@@ -337,6 +338,19 @@ def deposit_rho(grid, parts, bins, flags=0, rho=None):
     _check(lib().pic_deposit_rho(ctypes.byref(grid.c), ctypes.byref(pc), bins.h, _ptr(rho),
                                  flags, _stream()))
     return rho
+
+
+def gather_fields(grid, parts, bins, E, B):
+    """E and B at every slot (pic_gather_fields): two lists of three float32 tensors."""
+    n = parts.nslots
+    dev = parts.x.device
+    out = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(6)]
+    F = [f.contiguous() for f in list(E) + list(B)]
+    pc = parts.c()
+    _check(lib().pic_gather_fields(ctypes.byref(grid.c), ctypes.byref(pc),
+                                   bins.h if bins else None, *[_ptr(f) for f in F],
+                                   *[_ptr(o) for o in out], _stream()))
+    return out[:3], out[3:]
 
 
 def deposit_backward(grid, parts, bins, G, want_dw=True):
