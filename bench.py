@@ -175,6 +175,9 @@ def main():
         out["charge_density"] = rho_line(pic, torch, grid, parts, bins, N, ncell)
         out["field_gather"] = gather_line(pic, torch, grid, parts, bins, N, ncell)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        bw = copy_bandwidth(torch)
+        out["hbm_copy_GBps"] = bw
+        out["roofline"]["frac_vs_measured_copy"] = achieved / bw
     bins.close()
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
@@ -425,6 +428,15 @@ def gather_line(pic, torch, grid, parts, bins, N, ncell):
     byts = N * (24 + 24) + 6 * ncell * 4     # positions in, six values out, six grids in
     return {"particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
             "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "rel_l2_vs_oracle_32cubed": err}
+
+
+def copy_bandwidth(torch):
+    """Device-to-device copy rate of a 1 GiB buffer (read + write bytes / time), the
+    measured counterpart of the 8 TB/s HBM figure."""
+    src = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = _events_ms(torch, lambda: dst.copy_(src), 10)
+    return 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(sample):
