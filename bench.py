@@ -27,18 +27,22 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "deposit_cell_valu_c2_128cubed_o3_hbm_counters.md")
 
 
-def measured_traffic(path, tile, n, ppc):
+def measured_traffic(path, tile, n, ppc, slack):
     """HBM bytes per deposition call from the committed rocprofv3 counter summary, or None
-    when the summary does not match this workload or the deposition sources changed since
+    when the summary was taken on another workload or the deposition sources changed since
     the counters were taken."""
     import hashlib
-    if path not in ("auto", "cell_valu") or tile != (8, 8, 4) or n != 128 or ppc != 8:
+    if path not in ("auto", "cell_valu"):
         return None
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    kv = dict(l.split(": ", 1) for l in text.splitlines() if l.startswith(("traffic_", "source_")))
+    kv = dict(l.split(": ", 1) for l in text.splitlines()
+              if l.startswith(("traffic_", "source_", "workload_")))
+    want = f"n={n} ppc={ppc} tile={'x'.join(str(t) for t in tile)} slack={slack:g}"
+    if kv.get("workload_key") != want:
+        return None
     h = hashlib.sha256()
     for f in kv.get("source_files", "").split():
         try:
@@ -59,6 +63,7 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="cells per dimension")
     ap.add_argument("--ppc", type=int, default=8)
     ap.add_argument("--tile", default="8x8x4", help="particle tile, cells (x by y by z)")
+    ap.add_argument("--slack", type=float, default=0.5, help="free slots per bin, per particle")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
@@ -90,7 +95,7 @@ def main():
     params, arrays = synth.c2(n=n3, ppc=args.ppc)
     N = arrays["x"].size
     ncell = int(np.prod(n3))
-    slack = 0.25
+    slack = args.slack
     grid = pic.Grid(params)
     nslots = pic.slots_for(N, ncell, slack)
     parts = pic.Particles.from_arrays(arrays, nslots)
@@ -160,7 +165,7 @@ def main():
                    "slack": slack},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.path, tile, args.n, args.ppc),
+                     "traffic": measured_traffic(args.path, tile, args.n, args.ppc, slack),
                      "kernel": "pic_deposit call = k_dep_cell_valu<3,3> + k_halo_sum<3,3> "
                                "(fused drift + mover detection)",
                      "bytes_per_launch": dep_bytes, "kernel_ms": dep_ms},

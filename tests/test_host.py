@@ -44,14 +44,15 @@ def test_bench_traffic_reader(tmp_path, monkeypatch):
     sha = hashlib.sha256(b"kernel source").hexdigest()
     prof = tmp_path / "p.md"
     prof.write_text(f"# x\n\ntraffic_bytes_per_launch: 12345\nsource_sha256: {sha}\n"
-                    f"source_files: a.txt\n")
+                    f"source_files: a.txt\nworkload_key: n=128 ppc=8 tile=8x8x4 slack=0.5\n")
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("auto", (8, 8, 4), 128, 8) == 12345.0
-    assert bench.measured_traffic("mfma_bf16", (8, 8, 4), 128, 8) is None   # other kernel
-    assert bench.measured_traffic("auto", (8, 8, 8), 128, 8) is None        # other workload
+    assert bench.measured_traffic("auto", (8, 8, 4), 128, 8, 0.5) == 12345.0
+    assert bench.measured_traffic("mfma_bf16", (8, 8, 4), 128, 8, 0.5) is None   # other kernel
+    assert bench.measured_traffic("auto", (8, 8, 8), 128, 8, 0.5) is None        # other tile
+    assert bench.measured_traffic("auto", (8, 8, 4), 128, 8, 0.25) is None       # other slack
     src.write_text("changed source")
-    assert bench.measured_traffic("auto", (8, 8, 4), 128, 8) is None        # stale counters
+    assert bench.measured_traffic("auto", (8, 8, 4), 128, 8, 0.5) is None        # stale counters
 
 
 def test_bench_refuses_more_than_one_gpu():
