@@ -5,7 +5,8 @@
 // device-wide work list of (patch, tile) items. A plan fixes the patches, their bins and
 // the work list (longest items first, by particles per tile x stencil volume); every call
 // then enqueues three kernels (zero J / reset counters, the persistent per-cell
-// deposition pulling items from a device counter, the tile-window sum into J), with no
+// deposition pulling items from a device counter, the tile-window sum into J, one
+// workgroup per item), with no
 // allocation, no host synchronisation and no memset node, so it can be captured into a
 // HIP graph.
 #include <algorithm>
@@ -29,6 +30,7 @@ struct pic_plan {
   int nitems = 0;
   int* d_queue = nullptr;
   size_t smem = 0;
+  size_t halo_smem = 0;
   int blocks = 0;
   int blocks_per_cu = 0;
   int64_t max_nodes = 0;
@@ -93,6 +95,7 @@ extern "C" pic_status pic_plan_create(const pic_grid* grids, int npatch, pic_bin
       return set_error(PIC_ERR_UNSUPPORTED, "tile too large for LDS in a batched launch");
     }
     p->smem = std::max(p->smem, sm);
+    p->halo_smem = std::max(p->halo_smem, halo_smem_bytes(kb));
     max_lds = bins[k]->max_lds;
     p->grids.push_back(grids[k]);
     p->bins.push_back(bins[k]);
@@ -187,7 +190,7 @@ extern "C" pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* p
   batched_prologue_launch(plan->d_pd, plan->npatch, plan->max_nodes, plan->d_queue, flags, stream);
   batched_cell_launch(plan->d_pd, plan->d_items, plan->nitems, plan->d_queue, plan->blocks,
                       plan->smem, flags, stream);
-  batched_halo_launch(plan->d_pd, plan->npatch, plan->max_nodes, stream);
+  batched_halo_tile_launch(plan->d_pd, plan->d_items, plan->nitems, plan->halo_smem, stream);
   for (int k = 0; k < plan->npatch; ++k) {
     if (flags & PIC_F_EMIT_MOVERS) plan->bins[k]->movers_fresh = true;
     else if (flags & PIC_F_DRIFT) plan->bins[k]->movers_fresh = false;

@@ -6,7 +6,7 @@
 //                    read with coalesced loads, their 3 (O+1)^DIM contributions added
 //                    with ds_add_f32 into an LDS window covering the tile plus its stencil
 //                    halo, and the window is stored once (tile-level reduction, the
-//                    rhocell -> grid step of Eq. 5 at tile granularity); k_halo_sum then
+//                    rhocell -> grid step of Eq. 5 at tile granularity); k_halo_tile then
 //                    adds the overlapping windows of neighbouring tiles into J. Particles whose
 //                    cell no longer matches their bin are deposited exactly (LDS when the
 //                    stencil fits the window, global atomics otherwise) and, with
@@ -178,94 +178,6 @@ __global__ __launch_bounds__(256) void k_dep_tile_atomic(KGrid G, KBins B, KPart
 // J += sum of the stored tile windows covering each node (at most 2 tiles per
 // dimension for tiles at least as wide as the stencil reach). One thread per node, all
 // three components.
-// Sums over the tile windows that cover node idx (flat, stored layout), per window copy.
-template <int O, int DIM>
-__device__ __forceinline__ void halo_sums(const KGrid& G, const KBins& B, int64_t idx, float& s0,
-                                          float& s1, float& s2) {
-  constexpr int LO = TileWin<O, DIM>::LO, R = TileWin<O, DIM>::R;
-  const int n3[3] = {(int)(idx % G.N[0]), (int)((idx / G.N[0]) % G.N[1]),
-                     (int)(idx / ((int64_t)G.N[0] * G.N[1]))};
-  int tl[3][6], wl[3][6], cnt[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    cnt[d] = 0;
-    if (d >= DIM) {
-      tl[d][0] = 0;
-      wl[d][0] = 0;
-      cnt[d] = 1;
-      continue;
-    }
-    if (G.per[d]) {
-      for (int k = -1; k <= 1; ++k)
-        cnt[d] = halo_cands(n3[d] + k * G.n[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d],
-                            cnt[d]);
-    } else {
-      cnt[d] = halo_cands(n3[d] - G.g[d], G.n[d], B.T[d], B.nt[d], LO, R, tl[d], wl[d], cnt[d]);
-    }
-  }
-  s0 = 0.f;
-  s1 = 0.f;
-  s2 = 0.f;
-  for (int a = 0; a < cnt[2]; ++a)
-    for (int b = 0; b < cnt[1]; ++b)
-      for (int c = 0; c < cnt[0]; ++c) {
-        const int t = tl[0][c] + B.nt[0] * (tl[1][b] + B.nt[1] * tl[2][a]);
-        const int W0 = min(B.T[0], G.n[0] - tl[0][c] * B.T[0]) + R;
-        const int W1 = DIM >= 2 ? min(B.T[1], G.n[1] - tl[1][b] * B.T[1]) + R : 1;
-        const int li = (wl[2][a] * W1 + wl[1][b]) * W0 + wl[0][c];
-        const float* src = B.wscr + (int64_t)t * 3 * B.wmax + li;
-        s0 += src[0];
-        s1 += src[B.wmax];
-        s2 += src[2 * B.wmax];
-      }
-}
-
-// J node idx = sum over the tile windows that cover it.
-template <int O, int DIM>
-__device__ __forceinline__ void halo_node(const KGrid& G, const KBins& B, float* __restrict__ J0,
-                                          float* __restrict__ J1, float* __restrict__ J2,
-                                          int64_t idx) {
-  float s0, s1, s2;
-  halo_sums<O, DIM>(G, B, idx, s0, s1, s2);
-  J0[idx] += s0;
-  J1[idx] += s1;
-  J2[idx] += s2;
-}
-
-// Charge density: the three window copies of each covering tile, summed.
-template <int O, int DIM>
-__global__ __launch_bounds__(256) void k_halo_rho(KGrid G, KBins B, float* __restrict__ rho) {
-  const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride) {
-    float s0, s1, s2;
-    halo_sums<O, DIM>(G, B, idx, s0, s1, s2);
-    rho[idx] += (s0 + s1) + s2;
-  }
-}
-
-void halo_rho_launch(const KGrid& G, pic_bins* b, float* rho, hipStream_t s) {
-  const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
-  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 16384));
-#define HR(O_, D_) hipLaunchKernelGGL((k_halo_rho<O_, D_>), dim3(blocks), dim3(256), 0, s, G, b->kb, rho)
-  if (G.dim == 3) {
-    if (G.order == 1) HR(1, 3); else if (G.order == 2) HR(2, 3); else HR(3, 3);
-  } else {
-    if (G.order == 1) HR(1, 2); else if (G.order == 2) HR(2, 2); else HR(3, 2);
-  }
-#undef HR
-}
-
-template <int O, int DIM>
-__global__ __launch_bounds__(256) void k_halo_sum(KGrid G, KBins B, float* __restrict__ J0,
-                                                  float* __restrict__ J1,
-                                                  float* __restrict__ J2) {
-  const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride)
-    halo_node<O, DIM>(G, B, J0, J1, J2, idx);
-}
-
 // Batched launches: blockIdx.y = patch.
 __global__ __launch_bounds__(256) void k_batched_prologue(const BatchPatch* __restrict__ pd,
                                                           int* __restrict__ queue, unsigned flags) {
@@ -287,39 +199,179 @@ __global__ __launch_bounds__(256) void k_batched_prologue(const BatchPatch* __re
   }
 }
 
-__global__ __launch_bounds__(256) void k_batched_halo(const BatchPatch* __restrict__ pd) {
-  const BatchPatch& d = pd[blockIdx.y];
-  const int64_t tot = (int64_t)d.G.N[0] * d.G.N[1] * d.G.N[2];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int order = d.G.order;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot; idx += stride) {
-    if (order == 1) halo_node<1, 3>(d.G, d.B, d.J[0], d.J[1], d.J[2], idx);
-    else if (order == 2) halo_node<2, 3>(d.G, d.B, d.J[0], d.J[1], d.J[2], idx);
-    else halo_node<3, 3>(d.G, d.B, d.J[0], d.J[1], d.J[2], idx);
-  }
-}
-
 void batched_prologue_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, int* queue,
                              unsigned flags, hipStream_t s) {
   const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_nodes + 255) / 256, 512));
   hipLaunchKernelGGL(k_batched_prologue, dim3(bx, npatch), dim3(256), 0, s, pd, queue, flags);
 }
 
-void batched_halo_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, hipStream_t s) {
-  const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_nodes + 255) / 256, 512));
-  hipLaunchKernelGGL(k_batched_halo, dim3(bx, npatch), dim3(256), 0, s, pd);
+// Tile-centric window sum: workgroup t owns the J nodes of its cells (on a guard dimension
+// the first and last tiles also own the stencil nodes beyond the domain) and adds, for each
+// of them, the entries of every tile window that covers it: its own and, near its faces,
+// the neighbours' (periodic neighbours across the boundary shifted by n). The stencil
+// reaches at most 2 nodes out; a ragged last tile may be a single cell wide, so tiles up to
+// three positions away are examined. Each stored node is written by exactly one workgroup.
+// RHO: the three window copies of the charge density are summed into J0.
+constexpr int HALO_MAXC = 6;      // candidate windows per dimension
+
+template <int O, int DIM, bool RHO>
+__device__ __forceinline__ void halo_tile_body(const KGrid& G, const KBins& B,
+                                               float* __restrict__ J0, float* __restrict__ J1,
+                                               float* __restrict__ J2, int tile, int32_t* sh) {
+  constexpr int LO = TileWin<O, DIM>::LO, R = TileWin<O, DIM>::R;
+  const TileBox tb = tile_box(G.n, B.T, B.nt, tile);
+  int tcoord[3];
+  {
+    int t = tile;
+    tcoord[0] = t % B.nt[0];
+    t /= B.nt[0];
+    tcoord[1] = t % B.nt[1];
+    tcoord[2] = t / B.nt[1];
+  }
+  // own node range per dimension
+  int a[3], len[3], off[3];
+  int tot = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d >= DIM) {
+      a[d] = 0;
+      len[d] = 1;
+    } else {
+      a[d] = tb.c0[d];
+      int b = tb.c0[d] + tb.e[d];
+      if (!G.per[d]) {
+        if (tcoord[d] == 0) a[d] = tb.c0[d] + LO;
+        if (tcoord[d] == B.nt[d] - 1) b = tb.c0[d] + tb.e[d] + R + LO;
+      }
+      len[d] = b - a[d];
+    }
+    off[d] = tot;
+    tot += len[d];
+  }
+  // candidates per own coordinate: count, neighbour tile coordinate, window coordinate,
+  // window width
+  int32_t* s_cnt = sh;
+  int32_t* s_t = s_cnt + tot;
+  int32_t* s_w = s_t + HALO_MAXC * tot;
+  int32_t* s_W = s_w + HALO_MAXC * tot;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int d = i >= off[2] ? 2 : (i >= off[1] ? 1 : 0);
+    const int m = a[d] + (i - off[d]);
+    int cnt = 0;
+    if (d >= DIM) {
+      s_t[i * HALO_MAXC] = 0;
+      s_w[i * HALO_MAXC] = 0;
+      s_W[i * HALO_MAXC] = 1;
+      cnt = 1;
+    } else {
+      for (int k = -3; k <= 3; ++k) {
+        int tn = tcoord[d] + k;
+        int shift = 0;
+        if (tn < 0 || tn >= B.nt[d]) {
+          if (!G.per[d]) continue;
+          // periodic image: wrap the tile index, shift its cells by whole domains
+          const int wraps = tn < 0 ? -((-tn + B.nt[d] - 1) / B.nt[d]) : tn / B.nt[d];
+          shift = wraps * G.n[d];
+          tn -= wraps * B.nt[d];
+        }
+        const int c0 = tn * B.T[d] + shift;
+        const int e = min(B.T[d], G.n[d] - tn * B.T[d]);
+        const int w = m - (c0 + LO);
+        if (w >= 0 && w < e + R && cnt < HALO_MAXC) {
+          s_t[i * HALO_MAXC + cnt] = tn;
+          s_w[i * HALO_MAXC + cnt] = w;
+          s_W[i * HALO_MAXC + cnt] = e + R;
+          ++cnt;
+        }
+      }
+    }
+    s_cnt[i] = cnt;
+  }
+  __syncthreads();
+  const int nn = len[0] * len[1] * len[2];
+  for (int q = threadIdx.x; q < nn; q += blockDim.x) {
+    const int ix = q % len[0], iy = (q / len[0]) % len[1], iz = q / (len[0] * len[1]);
+    const int i0 = off[0] + ix, i1 = off[1] + iy, i2 = off[2] + iz;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    for (int cz = 0; cz < s_cnt[i2]; ++cz)
+      for (int cy = 0; cy < s_cnt[i1]; ++cy)
+        for (int cx = 0; cx < s_cnt[i0]; ++cx) {
+          const int t = s_t[i0 * HALO_MAXC + cx] +
+                        B.nt[0] * (s_t[i1 * HALO_MAXC + cy] + B.nt[1] * s_t[i2 * HALO_MAXC + cz]);
+          const int li = (s_w[i2 * HALO_MAXC + cz] * s_W[i1 * HALO_MAXC + cy] +
+                          s_w[i1 * HALO_MAXC + cy]) * s_W[i0 * HALO_MAXC + cx] +
+                         s_w[i0 * HALO_MAXC + cx];
+          const float* src = B.wscr + (int64_t)t * 3 * B.wmax + li;
+          s0 += src[0];
+          s1 += src[B.wmax];
+          s2 += src[2 * B.wmax];
+        }
+    const int sx = store_idx(G, 0, a[0] + ix), sy = store_idx(G, 1, a[1] + iy);
+    const int sz = DIM == 3 ? store_idx(G, 2, a[2] + iz) : 0;
+    const int64_t idx = ((int64_t)sz * G.N[1] + sy) * G.N[0] + sx;
+    if constexpr (RHO) {
+      J0[idx] += (s0 + s1) + s2;
+    } else {
+      J0[idx] += s0;
+      J1[idx] += s1;
+      J2[idx] += s2;
+    }
+  }
 }
 
-template <int O, int DIM>
-static void launch_halo(const KGrid& G, pic_bins* b, float* J0, float* J1, float* J2,
-                        hipStream_t s) {
-  const int64_t tot = (int64_t)G.N[0] * G.N[1] * G.N[2];
-  unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tot + 255) / 256, 16384));
-  hipLaunchKernelGGL((k_halo_sum<O, DIM>), dim3(blocks), dim3(256), 0, s, G, b->kb, J0, J1, J2);
+template <int O, int DIM, bool RHO>
+__global__ __launch_bounds__(256) void k_halo_tile(KGrid G, KBins B, float* __restrict__ J0,
+                                                   float* __restrict__ J1,
+                                                   float* __restrict__ J2) {
+  extern __shared__ __align__(16) int32_t sh[];
+  halo_tile_body<O, DIM, RHO>(G, B, J0, J1, J2, blockIdx.x, sh);
+}
+
+// Batched window sum: one workgroup per (patch, tile) work item of the plan.
+__global__ __launch_bounds__(256) void k_batched_halo_tile(const BatchPatch* __restrict__ pd,
+                                                           const int2* __restrict__ items) {
+  extern __shared__ __align__(16) int32_t sh[];
+  const int pi = __builtin_amdgcn_readfirstlane(items[blockIdx.x].x);
+  const int tile = __builtin_amdgcn_readfirstlane(items[blockIdx.x].y);
+  const BatchPatch& d = pd[pi];
+  if (d.G.order == 1) halo_tile_body<1, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, sh);
+  else if (d.G.order == 2) halo_tile_body<2, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, sh);
+  else halo_tile_body<3, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, sh);
+}
+
+size_t halo_smem_bytes(const KBins& kb) {
+  int tot = 0;
+  for (int d = 0; d < 3; ++d) tot += kb.T[d] + 4;
+  return (size_t)tot * (1 + 3 * HALO_MAXC) * sizeof(int32_t);
+}
+
+void batched_halo_tile_launch(const BatchPatch* pd, const int2* items, int nitems, size_t smem,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_batched_halo_tile, dim3(nitems), dim3(256), smem, s, pd, items);
+}
+
+template <int O, int DIM, bool RHO>
+static void launch_halo_tile(const KGrid& G, pic_bins* b, float* J0, float* J1, float* J2,
+                             hipStream_t s) {
+  int tot = 0;
+  for (int d = 0; d < 3; ++d) tot += d < DIM ? b->kb.T[d] + TileWin<O, DIM>::R : 1;
+  const size_t smem = (size_t)tot * (1 + 3 * HALO_MAXC) * sizeof(int32_t);
+  hipLaunchKernelGGL((k_halo_tile<O, DIM, RHO>), dim3(b->kb.ntiles), dim3(256), smem, s, G,
+                     b->kb, J0, J1, J2);
+}
+
+void halo_rho_launch(const KGrid& G, pic_bins* b, float* rho, hipStream_t s) {
+#define HR(O_, D_) launch_halo_tile<O_, D_, true>(G, b, rho, rho, rho, s)
+  if (G.dim == 3) {
+    if (G.order == 1) HR(1, 3); else if (G.order == 2) HR(2, 3); else HR(3, 3);
+  } else {
+    if (G.order == 1) HR(1, 2); else if (G.order == 2) HR(2, 2); else HR(3, 2);
+  }
+#undef HR
 }
 
 void halo_launch(const KGrid& G, pic_bins* b, float* J0, float* J1, float* J2, hipStream_t s) {
-#define HL(O_, D_) launch_halo<O_, D_>(G, b, J0, J1, J2, s)
+#define HL(O_, D_) launch_halo_tile<O_, D_, false>(G, b, J0, J1, J2, s)
   if (G.dim == 3) {
     if (G.order == 1) HL(1, 3); else if (G.order == 2) HL(2, 3); else HL(3, 3);
   } else {

@@ -18,7 +18,7 @@
 //             share a word. LDS float atomics cost about 190 cycles per wave instruction
 //             on gfx950 (integer ones about 5) and are not used.
 //  end        the consumers add the stale particles (one at a time, lanes = stencil nodes)
-//             and the tile window goes to the window scratch; k_halo_sum adds neighbouring
+//             and the tile window goes to the window scratch; k_halo_tile adds neighbouring
 //             tiles into J.
 // Staggered axes use a window one node wider than the stencil (the stencil of a particle
 // in cell i starts at i + lo or i + lo + 1 depending on which half of the cell it is in);

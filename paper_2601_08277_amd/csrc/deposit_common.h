@@ -171,7 +171,7 @@ __device__ __forceinline__ int slot_bin(const int32_t* s_off, int nb, int s) {
 }
 
 // Store the tile's window to its slab of the window scratch (plain coalesced stores);
-// k_halo_sum then adds the overlapping windows of neighbouring tiles into J, so no
+// k_halo_tile then adds the overlapping windows of neighbouring tiles into J, so no
 // global atomics are needed (and the sum is deterministic).
 template <int O, int DIM>
 __device__ __forceinline__ void store_window(const KBins& B, int tile, const TileWin<O, DIM>& tw,
@@ -179,25 +179,6 @@ __device__ __forceinline__ void store_window(const KBins& B, int tile, const Til
   float* dst = B.wscr + (int64_t)tile * 3 * B.wmax;
   for (int c = 0; c < 3; ++c)
     for (int i = tid; i < tw.size; i += nthr) dst[(int64_t)c * B.wmax + i] = win[c * tw.size + i];
-}
-
-// Window of the tiles along one dimension that contain unwrapped node m:
-// appends (tile, index inside the window) pairs; returns the new count.
-__device__ __forceinline__ int halo_cands(int m, int n, int T, int nt, int LO, int R, int* tl,
-                                          int* wl, int cnt) {
-  int th = (m - LO) >= 0 ? (m - LO) / T : -((LO - m + T - 1) / T);
-  for (int t = th; t >= 0 && t >= th - 2; --t) {
-    if (t >= nt) continue;
-    int c0 = t * T;
-    int e = min(T, n - c0);
-    int w0 = c0 + LO;
-    if (m >= w0 && m < w0 + e + R && cnt < 6) {
-      tl[cnt] = t;
-      wl[cnt] = m - w0;
-      ++cnt;
-    }
-  }
-  return cnt;
 }
 
 // One patch of a batched launch, as the persistent kernels read it.
@@ -216,7 +197,9 @@ void batched_cell_launch(const BatchPatch* pd, const int2* items, int nitems, in
                          int blocks, size_t smem, unsigned flags, hipStream_t s);
 void batched_prologue_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, int* queue,
                              unsigned flags, hipStream_t s);
-void batched_halo_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, hipStream_t s);
+size_t halo_smem_bytes(const KBins& kb);
+void batched_halo_tile_launch(const BatchPatch* pd, const int2* items, int nitems, size_t smem,
+                              hipStream_t s);
 
 // Charge density on the per-cell path (deposit_cell.hip) and its window sum (deposit.hip).
 bool deposit_rho_cell_launch(const KGrid& G, const KPart& P, pic_bins* b, float* rho,
