@@ -421,17 +421,43 @@ __global__ __launch_bounds__(256) void k_compact(KBins B, KPart P) {
     const int total = L + I;
     const int nl = total - out;
     // swap-with-last: holes below nl take the valid entries at or above nl, in order
-    int top = nl;
-    for (int i = 0; i < nl; ++i) {
-      if (P.id[o + i] != PIC_INVALID_ID) continue;
-      while (top < total && P.id[o + top] == PIC_INVALID_ID) ++top;
-      if (top >= total) break;
-      copy_slot(P, o + i, P, o + top);
-      set_gap(P, o + top);
-      ++top;
+    if (total <= 16) {
+      // ids read at once (independent loads), holes and sources as bit masks
+      int32_t ids[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) ids[k] = k < total ? P.id[o + k] : 0;
+      unsigned holes = 0u, srcs = 0u, tail_gaps = 0u;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const bool gap = k < total && ids[k] == PIC_INVALID_ID;
+        if (k < nl && gap) holes |= 1u << k;
+        if (k >= nl && k < total && !gap) srcs |= 1u << k;
+        if (k >= nl && gap) tail_gaps |= 1u << k;
+      }
+      while (holes && srcs) {
+        const int h = __builtin_ctz(holes), t = __builtin_ctz(srcs);
+        copy_slot(P, o + h, P, o + t);
+        set_gap(P, o + t);
+        holes &= holes - 1u;
+        srcs &= srcs - 1u;
+      }
+      while (tail_gaps) {
+        set_gap(P, o + __builtin_ctz(tail_gaps));
+        tail_gaps &= tail_gaps - 1u;
+      }
+    } else {
+      int top = nl;
+      for (int i = 0; i < nl; ++i) {
+        if (P.id[o + i] != PIC_INVALID_ID) continue;
+        while (top < total && P.id[o + top] == PIC_INVALID_ID) ++top;
+        if (top >= total) break;
+        copy_slot(P, o + i, P, o + top);
+        set_gap(P, o + top);
+        ++top;
+      }
+      for (int i = nl; i < total; ++i)
+        if (P.id[o + i] == PIC_INVALID_ID) set_gap(P, o + i);
     }
-    for (int i = nl; i < total; ++i)
-      if (P.id[o + i] == PIC_INVALID_ID) set_gap(P, o + i);
     B.len[b] = nl;
     B.moved_out[b] = 0;
     B.ins_cnt[b] = 0;
