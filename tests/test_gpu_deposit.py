@@ -144,3 +144,33 @@ def test_out_of_domain_and_nan_are_reported():
         bins.check()
     assert e.value.status == -5
     bins.close()
+
+
+def test_dense_cells_multiple_units_and_map_windows():
+    """A few cells with ~150 particles: a group spans several stage units and several
+    slot-map windows; every path still matches the oracle."""
+    from paper_2601_08277_amd import pic
+    say("case dense cells")
+    rng = np.random.default_rng(17)
+    n = (12, 12, 12)
+    counts = rng.poisson(3.0, size=int(np.prod(n)))
+    counts[rng.choice(counts.size, 12, replace=False)] = 150
+    x, y, z = synth._place(rng, 3, n, counts)
+    u = [rng.normal(0, 0.2, x.size) for _ in range(3)]
+    arrays = synth._finish(rng, x, y, z, u)
+    params = synth._params(3, n, 3, -1.0, (0, 0, 0), 0, 0.2)
+    grid, og, parts, bins = setup(params, arrays, tile=(8, 8, 4))
+    want = oracle_J(og, arrays)
+    for path in ("cell_valu", "atomic", "mfma_fp16"):
+        J = pic.deposit(grid, parts, bins, path)
+        torch.cuda.synchronize()
+        tol = TOL_SPLIT if path.startswith("mfma") else TOL_FP32
+        errs = [rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)]
+        assert max(errs) <= tol, (path, errs)
+    rho = pic.deposit_rho(grid, parts, bins)
+    torch.cuda.synchronize()
+    from oracle import deposit as od
+    wr = od.deposit_rho(og, [arrays["x"], arrays["y"], arrays["z"]], arrays["w"])
+    assert rel_l2(rho.cpu().numpy(), wr) <= TOL_FP32
+    bins.check()
+    bins.close()
