@@ -405,3 +405,32 @@ def drift(g, pos, u, dt):
             xn = t + g.x0[d]
         out.append(xn)
     return out
+
+
+def boris_push(g, pos, u, E, B, qm, dt, valid=None):
+    """Relativistic Boris push (the particle push between depositions; the paper's Alg. 1
+    leaves it to the host code). Units c = 1, fields at the particles from gather_fields,
+    qm the charge-to-mass ratio, h = qm dt / 2:
+        u- = u + h E;  t = h B / gamma(u-);  s = 2 t / (1 + |t|^2)
+        u' = u- + u- x t;  u+ = u- + u' x s;  u_new = u+ + h E
+    u_new is stored as float32; the position then moves with that stored momentum exactly as
+    drift() does. Returns (new positions, new momenta as float32 arrays)."""
+    pos = _select(pos, valid)
+    u = _select(u, valid)
+    Ep, Bp = gather_fields(g, pos, E, B)
+    h = 0.5 * qm * dt
+    um = [np.asarray(u[c], dtype=np.float64) + h * Ep[c] for c in range(3)]
+    gm = np.sqrt(1.0 + (um[0] * um[0] + um[1] * um[1]) + um[2] * um[2])
+    t = [h * Bp[c] / gm for c in range(3)]
+    t2 = (t[0] * t[0] + t[1] * t[1]) + t[2] * t[2]
+    sv = [2.0 * t[c] / (1.0 + t2) for c in range(3)]
+
+    def cross(a, b):
+        return [a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]]
+
+    c1 = cross(um, t)
+    up = [um[c] + c1[c] for c in range(3)]
+    c2 = cross(up, sv)
+    upl = [um[c] + c2[c] for c in range(3)]
+    un = [(upl[c] + h * Ep[c]).astype(np.float32) for c in range(3)]
+    return drift(g, [np.asarray(p, dtype=np.float64) for p in pos], un, dt), un
