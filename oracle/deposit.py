@@ -434,3 +434,17 @@ def boris_push(g, pos, u, E, B, qm, dt, valid=None):
     upl = [um[c] + c2[c] for c in range(3)]
     un = [(upl[c] + h * Ep[c]).astype(np.float32) for c in range(3)]
     return drift(g, [np.asarray(p, dtype=np.float64) for p in pos], un, dt), un
+
+
+def deposit_midpoint(g, pos, u, w, dt, moved, valid=None):
+    """Time-centred current: Eq. 1 evaluated at the midpoint of the step's move x -> x + v dt
+    (leapfrog centring; the paper deposits at the stored positions and leaves the push to
+    the host code). `moved` says whether `pos` already holds the end of the move (after a
+    push: deposit at x - dt v / 2) or its start (the move follows in the same pass: deposit
+    at x + dt v / 2). The midpoint is formed with drift() over dt / 2, same operation order
+    and periodic wrap."""
+    pos = [np.asarray(p, dtype=np.float64) for p in _select(pos[: g.dim], valid)]
+    u = _select(u, valid)
+    w = _select([w], valid)[0]
+    mid = drift(g, pos, u, -0.5 * dt if moved else 0.5 * dt)
+    return deposit(g, mid, u, w)
