@@ -166,7 +166,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.path, tile, args.n, args.ppc, slack),
-                     "kernel": "pic_deposit call = k_dep_cell_valu<3,3> + k_halo_sum<3,3> "
+                     "kernel": "pic_deposit call = k_dep_cell_valu<3,3> + k_halo_tile<3,3> "
                                "(fused drift + mover detection)",
                      "bytes_per_launch": dep_bytes, "kernel_ms": dep_ms},
         "breakdown_ms": {"deposit": dep_ms, "rebin": reb_ms,
@@ -179,6 +179,9 @@ def main():
         out["paths"] = path_table(pic, torch, grid, parts, bins, N, ncell)
         out["charge_density"] = rho_line(pic, torch, grid, parts, bins, N, ncell)
         out["field_gather"] = gather_line(pic, torch, grid, parts, bins, N, ncell)
+        out["midpoint_deposit"] = midpoint_line(pic, torch, grid, parts, bins, N, ncell)
+        # last: the push moves the snapshot's particles
+        out["pic_cycle"] = cycle_line(pic, torch, grid, parts, bins, N, ncell)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
         bw = copy_bandwidth(torch)
         out["hbm_copy_GBps"] = bw
@@ -433,6 +436,90 @@ def gather_line(pic, torch, grid, parts, bins, N, ncell):
     byts = N * (24 + 24) + 6 * ncell * 4     # positions in, six values out, six grids in
     return {"particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
             "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "rel_l2_vs_oracle_32cubed": err}
+
+
+def _c2_small(pic):
+    from paper_2601_08277_amd import synth
+    sp, sa = synth.c2(n=(32, 32, 32))
+    sg = pic.Grid(sp)
+    s_slots = pic.slots_for(sa["x"].size, 32 ** 3, 0.25)
+    s_parts = pic.Particles.from_arrays(sa, s_slots)
+    s_bins = pic.Bins(sg, (8, 8, 4), 0.25, s_slots)
+    pic.rebin(sg, s_parts, s_bins, pic.REBIN_FULL)
+    return sp, sa, sg, s_parts, s_bins
+
+
+def midpoint_line(pic, torch, grid, parts, bins, N, ncell):
+    """Time-centred current (PIC_F_MIDPOINT, positions already pushed: deposit at
+    x - v dt/2) on the bench snapshot, with its rel-L2 against the FP64 oracle on the 32^3
+    scaled copy."""
+    from oracle import deposit as od
+    from oracle.deposit import OracleGrid
+    J = pic.new_J(grid)
+    ms = _events_ms(torch, lambda: pic.deposit(grid, parts, bins, "cell_valu", pic.F_MIDPOINT,
+                                               J=J), 10)
+    sp, sa, sg, s_parts, s_bins = _c2_small(pic)
+    got = pic.deposit(sg, s_parts, s_bins, "cell_valu", pic.F_MIDPOINT)
+    want = od.deposit_midpoint(OracleGrid.from_params(sp), [sa["x"], sa["y"], sa["z"]],
+                               [sa["ux"], sa["uy"], sa["uz"]], sa["w"], sp["dt"], moved=True)
+    err = max(float(np.linalg.norm(got[c].cpu().numpy() - want[c]) / np.linalg.norm(want[c]))
+              for c in range(3))
+    s_bins.close()
+    byts = N * 44 + 3 * ncell * 4
+    return {"particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
+            "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "rel_l2_vs_oracle_32cubed": err}
+
+
+def cycle_line(pic, torch, grid, parts, bins, N, ncell, steps=10):
+    """Particle side of a whole PIC step on the bench snapshot: pic_push (gather E, B +
+    Boris rotation + move), pic_deposit(PIC_F_MIDPOINT | PIC_F_EMIT_MOVERS) (time-centred
+    current, movers found against the pushed positions), pic_rebin(AUTO). E ~ N(0, 0.01),
+    B ~ N(0, 0.1), qm = -1, dt 0.2, order 3. Per-call times from HIP events on the launch
+    stream; the push's largest momentum error against the FP64 oracle on the 32^3 scaled
+    copy, relative to 1 + |u|."""
+    from oracle import deposit as od
+    from oracle.deposit import OracleGrid
+    g = torch.Generator(device="cuda").manual_seed(21)
+    E = [0.01 * torch.randn(grid.shape, generator=g, device="cuda") for _ in range(3)]
+    B = [0.1 * torch.randn(grid.shape, generator=g, device="cuda") for _ in range(3)]
+    J = pic.new_J(grid)
+    pol = pic.policy()
+    stream = torch.cuda.current_stream()
+    evs = []
+    for i in range(steps + 2):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record(stream)
+        pic.push(grid, parts, bins, E, B, -1.0, 0.2)
+        e[1].record(stream)
+        pic.deposit(grid, parts, bins, "auto", pic.F_MIDPOINT | pic.F_EMIT_MOVERS, J=J)
+        e[2].record(stream)
+        pic.rebin(grid, parts, bins, pic.REBIN_AUTO, pol)
+        e[3].record(stream)
+        if i >= 2:
+            evs.append(e)
+    torch.cuda.synchronize()
+    t = [float(np.mean([e[k].elapsed_time(e[k + 1]) for e in evs])) for k in range(3)]
+    sp, sa, sg, s_parts, s_bins = _c2_small(pic)
+    rng = np.random.default_rng(22)
+    Es = [rng.normal(0, 0.01, sg.shape).astype(np.float32) for _ in range(3)]
+    Bs = [rng.normal(0, 0.1, sg.shape).astype(np.float32) for _ in range(3)]
+    pic.push(sg, s_parts, s_bins, [torch.from_numpy(f).cuda() for f in Es],
+             [torch.from_numpy(f).cuda() for f in Bs], -1.0, 0.2)
+    host = s_parts.to_numpy()
+    valid = host["id"] != -1
+    order = np.argsort(host["id"][valid])
+    _, wu = od.boris_push(OracleGrid.from_params(sp), [sa["x"], sa["y"], sa["z"]],
+                          [sa["ux"], sa["uy"], sa["uz"]], [f.astype(np.float64) for f in Es],
+                          [f.astype(np.float64) for f in Bs], -1.0, 0.2)
+    err = max(float(np.max(np.abs(host[n][valid][order].astype(np.float64) - wu[c])
+                           / (1.0 + np.abs(wu[c]))))
+              for c, n in enumerate(("ux", "uy", "uz")))
+    s_bins.close()
+    push_bytes = N * (40 + 36) + 6 * ncell * 4   # x, u, id in; x, u out; six grids in
+    return {"particles_per_s": N / (sum(t) * 1e-3), "ms_per_step": sum(t),
+            "push_ms": t[0], "deposit_ms": t[1], "rebin_ms": t[2],
+            "push_hbm_frac": push_bytes / (t[0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "push_max_rel_u_err_vs_oracle_32cubed": err}
 
 
 def copy_bandwidth(torch):

@@ -74,8 +74,11 @@ enum {
   PIC_F_DETERMINISTIC = 2u,  /* reserved; bins are always kept in a deterministic order    */
   PIC_F_EMIT_MOVERS = 4u,    /* pic_deposit records particles whose cell no longer matches */
                              /* their bin, for the next PIC_REBIN_INCREMENTAL              */
-  PIC_F_DRIFT = 8u           /* pic_deposit then moves every particle x += v dt (grid dt)  */
+  PIC_F_DRIFT = 8u,          /* pic_deposit then moves every particle x += v dt (grid dt)  */
                              /* and records movers against the moved positions            */
+  PIC_F_MIDPOINT = 16u       /* time-centred current: deposit at the midpoint of the move  */
+                             /* x -> x + v dt (grid dt): at x + v dt / 2 with PIC_F_DRIFT, */
+                             /* else at x - v dt / 2 (x already advanced by a push)        */
 };
 
 #define PIC_INVALID_ID (-1)  /* id of an empty (gap) slot; gap slots also carry w = 0 */
@@ -91,7 +94,7 @@ typedef struct {
                     /* orders 1, 2, 3)                                            */
   int order;        /* shape order 1, 2 or 3                                      */
   float q;          /* charge of the species                                      */
-  double dt;        /* time step of PIC_F_DRIFT and pic_drift                      */
+  double dt;        /* time step of PIC_F_DRIFT, PIC_F_MIDPOINT and pic_drift       */
 } pic_grid;
 
 typedef struct {
@@ -185,7 +188,11 @@ pic_status pic_bins_report_perf(pic_bins* bins, double perf);
  * come from pic_rebin on these particles (any path except PIC_PATH_UNSORTED, which
  * ignores bins and may take NULL). Particles whose cell differs from their bin's cell are
  * still deposited exactly. With PIC_F_DRIFT the positions are advanced by v dt after
- * their current is deposited (periodic dimensions wrap). */
+ * their current is deposited (periodic dimensions wrap). PIC_F_MIDPOINT deposits each
+ * particle at x +- (dt/2) u / gamma, the offset formed in float32 and added to x in
+ * float64, wrapped on periodic dimensions (positions are not changed by it); it is taken by
+ * PIC_PATH_AUTO, PIC_PATH_CELL_VALU and PIC_PATH_UNSORTED (UNSUPPORTED on the other
+ * paths). */
 pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bins* bins,
                        float* Jx, float* Jy, float* Jz, int path, unsigned flags,
                        hipStream_t stream);
@@ -224,6 +231,23 @@ pic_status pic_gather_fields(const pic_grid* grid, const pic_particles* p, pic_b
                              const float* Bx, const float* By, const float* Bz, float* ex,
                              float* ey, float* ez, float* bx, float* by, float* bz,
                              hipStream_t stream);
+
+/* Particle push: the field gather above, then the relativistic Boris rotation and the move
+ * (the push half of the PIC cycle, Sec. 3.1, which the paper's Alg. 1 leaves to the host
+ * code). With c = 1 and h = qm dt / 2: u- = u + h E, t = h B / gamma(u-),
+ * s = 2 t / (1 + |t|^2), u+ = u- + (u- + u- x t) x s, u <- u+ + h E (float64 arithmetic,
+ * stored as float32), then x <- x + dt u / gamma(u) with the operation order and periodic
+ * wrap of pic_drift. qm: charge-to-mass ratio of the species; E, B: as for
+ * pic_gather_fields (device, read only). Updates x, y, z, ux, uy, uz of every valid
+ * particle in place; gap slots and out-of-domain particles are left alone. With bins the
+ * tile windows of the fields are read once into LDS (particles that left their tile are
+ * pushed from global memory), and the bins' mover list is marked stale, so the next
+ * pic_rebin detects movers itself. flags must be 0. Errors: INVALID_ARG (bad arguments,
+ * non-finite qm or dt, bins for another grid); out-of-domain positions and stencil nodes
+ * outside the stored grid are reported by pic_check. */
+pic_status pic_push(const pic_grid* grid, pic_particles* p, pic_bins* bins, const float* Ex,
+                    const float* Ey, const float* Ez, const float* Bx, const float* By,
+                    const float* Bz, double qm, double dt, unsigned flags, hipStream_t stream);
 
 /* Constant-velocity move of every valid particle, x += v dt (float64), with periodic
  * wrap: the stand-in for the particle push between steps. */

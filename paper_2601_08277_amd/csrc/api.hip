@@ -416,10 +416,14 @@ extern "C" pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bi
   if (st != PIC_OK) return st;
   if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
   if (!Jx || !Jy || !Jz) return set_error(PIC_ERR_INVALID_ARG, "J pointers must not be NULL");
-  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC | PIC_F_EMIT_MOVERS | PIC_F_DRIFT))
+  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC | PIC_F_EMIT_MOVERS | PIC_F_DRIFT |
+                          PIC_F_MIDPOINT))
     return set_error(PIC_ERR_INVALID_ARG, "unknown flag bits");
   if (path < PIC_PATH_AUTO || path > PIC_PATH_UNSORTED)
     return set_error(PIC_ERR_INVALID_ARG, "unknown deposition path");
+  if ((flags & PIC_F_MIDPOINT) && path != PIC_PATH_AUTO && path != PIC_PATH_CELL_VALU &&
+      path != PIC_PATH_UNSORTED)
+    return set_error(PIC_ERR_UNSUPPORTED, "PIC_F_MIDPOINT runs on the per-cell and unsorted paths");
   if (path != PIC_PATH_UNSORTED) {
     if (!b) return set_error(PIC_ERR_INVALID_ARG, "bins required for this path");
     if (!same_grid(*grid, b->grid)) return set_error(PIC_ERR_INVALID_ARG, "grid differs from the bins' grid");
@@ -428,7 +432,7 @@ extern "C" pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bi
   } else if (flags & PIC_F_EMIT_MOVERS) {
     return set_error(PIC_ERR_INVALID_ARG, "PIC_F_EMIT_MOVERS needs bins");
   }
-  if ((flags & PIC_F_DRIFT) && !std::isfinite(grid->dt))
+  if ((flags & (PIC_F_DRIFT | PIC_F_MIDPOINT)) && !std::isfinite(grid->dt))
     return set_error(PIC_ERR_INVALID_ARG, "dt must be finite");
   KGrid G = make_kgrid(*grid);
   KPart P = make_kpart(*p);

@@ -162,8 +162,10 @@ __global__ __launch_bounds__(256) void k_backward_tile(KGrid G, KBins B, KPart P
   extern __shared__ __align__(16) float sG[];
   const float* Gs[3] = {G0, G1, G2};
   uint32_t bad = 0;
-  if (blockIdx.x == (unsigned)B.ntiles) {
-    for (int s = B.off[B.nbins] + threadIdx.x; s < P.nslots; s += blockDim.x)
+  if (blockIdx.x >= (unsigned)B.ntiles) {
+    const int stride = TAIL_BLOCKS * blockDim.x;
+    for (int s = B.off[B.nbins] + (blockIdx.x - B.ntiles) * blockDim.x + threadIdx.x;
+         s < P.nslots; s += stride)
       bwd_zero(s, DIM, dx, dy, dz, dux, duy, duz, dw);
     return;
   }
@@ -242,7 +244,7 @@ static bool launch_bwd_tile(const KGrid& G, const KPart& P, const pic_bins* b, c
   if (smem > b->max_lds) return false;
   // the list count lives in the full sort's scratch counter, the list in its bin array
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->kb.ctr + CTR_TOTAL, (int64_t)1);
-  hipLaunchKernelGGL((k_backward_tile<O, DIM>), dim3(b->kb.ntiles + 1), dim3(256), smem, s, G,
+  hipLaunchKernelGGL((k_backward_tile<O, DIM>), dim3(b->kb.ntiles + TAIL_BLOCKS), dim3(256), smem, s, G,
                      b->kb, P, G0, G1, G2, dx, dy, dz, dux, duy, duz, dw, b->sbin);
   hipLaunchKernelGGL((k_backward_list<O, DIM>), dim3(256), dim3(256), 0, s, G, b->kb, P, G0, G1,
                      G2, dx, dy, dz, dux, duy, duz, dw, b->sbin);

@@ -144,7 +144,8 @@ extern "C" pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* p
   if (!plan || !particles || !J3) return set_error(PIC_ERR_INVALID_ARG, "NULL argument");
   if (path != PIC_PATH_AUTO && path != PIC_PATH_CELL_VALU)
     return set_error(PIC_ERR_UNSUPPORTED, "batched launches run the per-cell VALU path");
-  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC | PIC_F_EMIT_MOVERS | PIC_F_DRIFT))
+  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC | PIC_F_EMIT_MOVERS | PIC_F_DRIFT |
+                          PIC_F_MIDPOINT))
     return set_error(PIC_ERR_INVALID_ARG, "unknown flag bits");
   std::vector<BatchPatch> pd(plan->npatch);
   for (int k = 0; k < plan->npatch; ++k) {
@@ -158,7 +159,7 @@ extern "C" pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* p
       return set_error(PIC_ERR_INVALID_ARG, "bins are empty: run pic_rebin(PIC_REBIN_FULL) first");
     if (!J3[3 * k] || !J3[3 * k + 1] || !J3[3 * k + 2])
       return set_error(PIC_ERR_INVALID_ARG, "J pointers must not be NULL");
-    if ((flags & PIC_F_DRIFT) && !std::isfinite(g.dt))
+    if ((flags & (PIC_F_DRIFT | PIC_F_MIDPOINT)) && !std::isfinite(g.dt))
       return set_error(PIC_ERR_INVALID_ARG, "dt must be finite");
     std::memset(&pd[k], 0, sizeof(BatchPatch));
     pd[k].G = make_kgrid(g);

@@ -42,16 +42,18 @@ template <int O, int DIM>
 __global__ __launch_bounds__(256) void k_dep_unsorted(KGrid G, KPart P, float* __restrict__ J0,
                                                       float* __restrict__ J1,
                                                       float* __restrict__ J2, uint32_t* err,
-                                                      int drift, double dt) {
+                                                      int drift, double dt, float hdt) {
   const int stride = gridDim.x * blockDim.x;
   uint32_t bad = 0;
   float* J[3] = {J0, J1, J2};
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.nslots; s += stride) {
     if (P.id[s] == PIC_INVALID_ID) continue;
     double pos[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
+    const float ux = P.ux[s], uy = P.uy[s], uz = P.uz[s];
+    double dp[3] = {pos[0], pos[1], pos[2]};
+    if (hdt != 0.0f) midpoint_shift<DIM>(G, dp, ux, uy, uz, hdt);   // time-centred position
     PartPrep<O, DIM> p;
-    if (!prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad)) continue;
-    float ux = P.ux[s], uy = P.uy[s], uz = P.uz[s];
+    if (!prep_cell<DIM>(G, dp[0], dp[1], dp[2], p.cell, p.f, bad)) continue;
     prep_amp(G.q, ux, uy, uz, P.w[s], p.amp);
     prep_shapes(p);
     scatter_particle(p, [&](int c, int mx, int my, int mz, float v) {
@@ -404,11 +406,11 @@ void drift_launch(const KGrid& G, const KPart& P, double dt, hipStream_t s) {
 // -----------------------------------------------------------------------------------
 template <int O, int DIM>
 static void launch_unsorted(const KGrid& G, const KPart& P, float* J0, float* J1, float* J2,
-                            uint32_t* err, bool drift, double dt, hipStream_t s) {
+                            uint32_t* err, bool drift, double dt, float hdt, hipStream_t s) {
   unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)P.nslots + 255) / 256, 16384);
   if (blocks == 0) return;
   hipLaunchKernelGGL((k_dep_unsorted<O, DIM>), dim3(blocks), dim3(256), 0, s, G, P, J0, J1, J2,
-                     err, drift ? 1 : 0, dt);
+                     err, drift ? 1 : 0, dt, hdt);
 }
 
 template <int O, int DIM>
@@ -433,7 +435,8 @@ bool deposit_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, floa
   const bool drift = flags & PIC_F_DRIFT;
   if (!b) {
     uint32_t* err = nobins_err_ptr();
-#define UNS(O_, D_) launch_unsorted<O_, D_>(G, P, J0, J1, J2, err, drift, dt, s)
+    const float hdt = !(flags & PIC_F_MIDPOINT) ? 0.0f : (float)(drift ? 0.5 * dt : -0.5 * dt);
+#define UNS(O_, D_) launch_unsorted<O_, D_>(G, P, J0, J1, J2, err, drift, dt, hdt, s)
     if (G.dim == 3) {
       if (G.order == 1) UNS(1, 3); else if (G.order == 2) UNS(2, 3); else UNS(3, 3);
     } else {

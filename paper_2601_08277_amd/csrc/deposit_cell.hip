@@ -220,7 +220,7 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
                                          const TileBox& tb, const int32_t* s_off,
                                          const int32_t* s_len, const CellGroup& gr, float* sf,
                                          float* sa, int8_t* map, StaleRec* stale, int* s_nstale,
-                                         float* const* J, uint32_t& bad) {
+                                         float* const* J, uint32_t& bad, float hdt) {
   const int lane = threadIdx.x % PIC_WAVE;
   const int pw = threadIdx.x / PIC_WAVE - CV_CONS;   // producer index
   const int ex = tb.e[0], exy = tb.e[0] * tb.e[1];
@@ -268,6 +268,8 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
       double pos[3] = {r.x, r.y, r.z};
       bool ok = false, mine = false;
       if (r.lc >= 0) {
+        // time-centred deposition at x + hdt v (hdt = +-dt/2)
+        if (hdt != 0.0f) midpoint_shift<DIM>(G, pos, r.ux, r.uy, r.uz, hdt);
         ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad);
         if constexpr (RHO) {
           p.amp[0] = G.q * r.w;       // charge density: q W, no velocity
@@ -596,6 +598,8 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   if (threadIdx.x == 0) *s_nstale = 0;
   __syncthreads();
   uint32_t bad = 0;
+  const float hdt = (RHO || !(flags & PIC_F_MIDPOINT)) ? 0.0f
+                    : (float)((flags & PIC_F_DRIFT) ? 0.5 * dt : -0.5 * dt);
   CellGroup cur = cv_first_unit(0, s_off, s_len, tb.nb, lane);
   // The producer and the consumers run separate loops over the same units with one
   // barrier per unit (plus one after the first unit is staged), so the consumers'
@@ -603,7 +607,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   if (producer) {
     if (cur.g0 < tb.nb)
       cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, map_p, stale,
-                       s_nstale, J, bad);
+                       s_nstale, J, bad, hdt);
     __syncthreads();
     int ub = 0;
     while (cur.g0 < tb.nb) {
@@ -611,7 +615,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
       if (nxt.g0 < tb.nb) {
         float* nf = stage + (ub ^ 1) * 6 * CV_CAP;
         cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, map_p, stale,
-                         s_nstale, J, bad);
+                         s_nstale, J, bad, hdt);
       }
       __syncthreads();
       cur = nxt;

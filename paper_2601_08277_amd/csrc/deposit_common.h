@@ -101,6 +101,11 @@ struct SubWin {
 // and at the end of the tile (usually once per tile: the list counter is contended).
 constexpr int MBUF = 128;
 
+// Workgroups appended to a one-workgroup-per-tile launch that write the outputs of the
+// slots past the last bin (gaps) with a grid-stride loop; one workgroup alone would take
+// longer than the tiles for large slack.
+constexpr int TAIL_BLOCKS = 64;
+
 struct MoverBuf {
   int32_t* slot;
   int32_t* oldb;

@@ -7,6 +7,7 @@
 // of all six components into LDS, then its particles gather from LDS. Particles whose cell
 // is outside their tile are listed and gathered from global memory by k_gather_list.
 #include <algorithm>
+#include <cmath>
 
 #include "deposit_common.h"
 
@@ -103,9 +104,12 @@ __global__ __launch_bounds__(256) void k_gather_tile(KGrid G, KBins B, KPart P, 
                                                      GatherOut o, int32_t* __restrict__ list) {
   extern __shared__ __align__(16) float sF[];
   uint32_t bad = 0;
-  if (blockIdx.x == (unsigned)B.ntiles) {
+  if (blockIdx.x >= (unsigned)B.ntiles) {
     const float z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int s = B.off[B.nbins] + threadIdx.x; s < P.nslots; s += blockDim.x) gather_write(o, s, z);
+    const int stride = TAIL_BLOCKS * blockDim.x;
+    for (int s = B.off[B.nbins] + (blockIdx.x - B.ntiles) * blockDim.x + threadIdx.x;
+         s < P.nslots; s += stride)
+      gather_write(o, s, z);
     return;
   }
   const TileBox tb = tile_box(G.n, B.T, B.nt, blockIdx.x);
@@ -165,7 +169,7 @@ static void launch_gather(const KGrid& G, const KPart& P, pic_bins* b, const Fie
   const size_t smem = b ? 6 * sizeof(float) * (size_t)TileWin<O, DIM>::max_size(b->kb) : 0;
   if (b && b->sorted_once && smem <= b->max_lds) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->kb.ctr + CTR_TOTAL, (int64_t)1);
-    hipLaunchKernelGGL((k_gather_tile<O, DIM>), dim3(b->kb.ntiles + 1), dim3(256), smem, s, G,
+    hipLaunchKernelGGL((k_gather_tile<O, DIM>), dim3(b->kb.ntiles + TAIL_BLOCKS), dim3(256), smem, s, G,
                        b->kb, P, F, o, b->sbin);
     hipLaunchKernelGGL((k_gather_list<O, DIM>), dim3(256), dim3(256), 0, s, G, b->kb, P, F, o,
                        b->sbin);
@@ -203,4 +207,176 @@ extern "C" pic_status pic_gather_fields(const pic_grid* grid, const pic_particle
   }
 #undef GA
   return check_hip(hipGetLastError(), "pic_gather_fields launch");
+}
+
+// ---------------------------------------------------------------------------------------
+// Particle push: the gather above followed by the relativistic Boris rotation (c = 1,
+// h = qm dt / 2) and the move, one pass over the particles. With u- = u + h E,
+// t = h B / gamma(u-), s = 2 t / (1 + |t|^2): u+ = u- + (u- + u- x t) x s, u <- u+ + h E
+// (rounded to float32), then x moves with the new u exactly as drift_one does. The
+// rotation runs in float64: its cost is small next to the gather and it keeps |u| to
+// float64 rounding through many pushes.
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* r) {
+  r[0] = a[1] * b[2] - a[2] * b[1];
+  r[1] = a[2] * b[0] - a[0] * b[2];
+  r[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <int DIM>
+__device__ __forceinline__ void boris_move(const KGrid& G, const KPart& P, int s, const float* v,
+                                           double h, double dt) {
+  double um[3] = {(double)P.ux[s] + h * (double)v[0], (double)P.uy[s] + h * (double)v[1],
+                  (double)P.uz[s] + h * (double)v[2]};
+  const double gm = __builtin_sqrt(1.0 + ((um[0] * um[0] + um[1] * um[1]) + um[2] * um[2]));
+  const double t[3] = {h * (double)v[3] / gm, h * (double)v[4] / gm, h * (double)v[5] / gm};
+  const double k = 2.0 / (1.0 + ((t[0] * t[0] + t[1] * t[1]) + t[2] * t[2]));
+  const double sv[3] = {k * t[0], k * t[1], k * t[2]};
+  double c[3], up[3];
+  cross3(um, t, c);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) up[d] = um[d] + c[d];
+  cross3(up, sv, c);
+  const float un[3] = {(float)(um[0] + c[0] + h * (double)v[0]),
+                       (float)(um[1] + c[1] + h * (double)v[1]),
+                       (float)(um[2] + c[2] + h * (double)v[2])};
+  P.ux[s] = un[0];
+  P.uy[s] = un[1];
+  P.uz[s] = un[2];
+  double pos[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
+  drift_one<DIM>(G, pos, un[0], un[1], un[2], dt);
+  P.x[s] = pos[0];
+  P.y[s] = pos[1];
+  if (DIM == 3) P.z[s] = pos[2];
+}
+
+// Particle-parallel push from global memory (no bins).
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_push(KGrid G, KPart P, FieldPtrs F, double h, double dt,
+                                              uint32_t* err) {
+  uint32_t bad = 0;
+  const FieldFetch ff{G, F.f, bad};
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.nslots; s += gridDim.x * blockDim.x) {
+    int cell[3];
+    float f[3];
+    if (P.id[s] == PIC_INVALID_ID ||
+        !prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad))
+      continue;
+    float v[6];
+    gather_particle<O, DIM>(cell, f, ff, v);
+    boris_move<DIM>(G, P, s, v, h, dt);
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+// One workgroup per tile: the six field windows into LDS, then every particle of the tile
+// whose stencil lies in the window is pushed from LDS. Particles outside their tile's
+// window are listed for k_push_list. Slots past the last bin are gaps (the bins hold every
+// valid particle) and are not visited.
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_push_tile(KGrid G, KBins B, KPart P, FieldPtrs F,
+                                                   double h, double dt,
+                                                   int32_t* __restrict__ list) {
+  extern __shared__ __align__(16) float sF[];
+  uint32_t bad = 0;
+  const TileBox tb = tile_box(G.n, B.T, B.nt, blockIdx.x);
+  const TileWin<O, DIM> tw(tb);
+  const int W01 = tw.W[0] * tw.W[1];
+  for (int i = threadIdx.x; i < 6 * tw.size; i += blockDim.x) {
+    const int c = i / tw.size;
+    const int r = i - c * tw.size;
+    const int wz = r / W01, wy = (r - wz * W01) / tw.W[0], wx = r - wz * W01 - wy * tw.W[0];
+    const int ix = store_idx(G, 0, tw.o[0] + wx), iy = store_idx(G, 1, tw.o[1] + wy);
+    const int iz = DIM == 3 ? store_idx(G, 2, tw.o[2] + wz) : 0;
+    sF[i] = (ix | iy | iz) >= 0 ? F.f[c][((int64_t)iz * G.N[1] + iy) * G.N[0] + ix] : 0.f;
+  }
+  __syncthreads();
+  auto lf = [&](int c, int mx, int my, int mz, float) -> float {
+    return sF[c * tw.size + ((mz - tw.o[2]) * tw.W[1] + (my - tw.o[1])) * tw.W[0] + (mx - tw.o[0])];
+  };
+  const int S0 = B.off[tb.b0], S1 = B.off[tb.b0 + tb.nb];
+  for (int base = S0; base < S1; base += blockDim.x) {
+    const int s = base + threadIdx.x;
+    int cell[3];
+    float f[3];
+    const bool ok = s < S1 && P.id[s] != PIC_INVALID_ID &&
+                    prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad);
+    const bool local = ok && tw.fits_cell(cell);
+    if (local) {
+      float v[6];
+      gather_particle<O, DIM>(cell, f, lf, v);
+      boris_move<DIM>(G, P, s, v, h, dt);
+    }
+    const int e = wave_append(ok && !local, &B.ctr[CTR_TOTAL]);
+    if (e >= 0) list[e] = s;
+  }
+  if (bad) atomicOr(B.err, bad);
+}
+
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_push_list(KGrid G, KBins B, KPart P, FieldPtrs F,
+                                                   double h, double dt,
+                                                   const int32_t* __restrict__ list) {
+  uint32_t bad = 0;
+  const FieldFetch ff{G, F.f, bad};
+  const int n = B.ctr[CTR_TOTAL];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int s = list[e];
+    int cell[3];
+    float f[3];
+    if (!prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad)) continue;
+    float v[6];
+    gather_particle<O, DIM>(cell, f, ff, v);
+    boris_move<DIM>(G, P, s, v, h, dt);
+  }
+  if (bad) atomicOr(B.err, bad);
+}
+
+template <int O, int DIM>
+static void launch_push(const KGrid& G, const KPart& P, pic_bins* b, const FieldPtrs& F,
+                        double h, double dt, hipStream_t s) {
+  const size_t smem = b ? 6 * sizeof(float) * (size_t)TileWin<O, DIM>::max_size(b->kb) : 0;
+  if (b && b->sorted_once && smem <= b->max_lds) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->kb.ctr + CTR_TOTAL, (int64_t)1);
+    hipLaunchKernelGGL((k_push_tile<O, DIM>), dim3(b->kb.ntiles), dim3(256), smem, s, G,
+                       b->kb, P, F, h, dt, b->sbin);
+    hipLaunchKernelGGL((k_push_list<O, DIM>), dim3(256), dim3(256), 0, s, G, b->kb, P, F, h, dt,
+                       b->sbin);
+    return;
+  }
+  const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)P.nslots + 255) / 256, 16384);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_push<O, DIM>), dim3(blocks), dim3(256), 0, s, G, P, F, h, dt,
+                     b ? b->kb.err : nobins_err_ptr());
+}
+
+extern "C" pic_status pic_push(const pic_grid* grid, pic_particles* p, pic_bins* b,
+                               const float* Ex, const float* Ey, const float* Ez,
+                               const float* Bx, const float* By, const float* Bz, double qm,
+                               double dt, unsigned flags, hipStream_t stream) {
+  pic_status st = validate_grid(grid);
+  if (st != PIC_OK) return st;
+  if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
+  if (!Ex || !Ey || !Ez || !Bx || !By || !Bz)
+    return set_error(PIC_ERR_INVALID_ARG, "field pointers must not be NULL");
+  if (!std::isfinite(qm) || !std::isfinite(dt))
+    return set_error(PIC_ERR_INVALID_ARG, "qm and dt must be finite");
+  if (flags != 0) return set_error(PIC_ERR_INVALID_ARG, "pic_push takes no flags");
+  if (b) {
+    if (!same_grid(*grid, b->grid)) return set_error(PIC_ERR_INVALID_ARG, "grid differs from the bins' grid");
+    if (p->nslots != b->nslots) return set_error(PIC_ERR_INVALID_ARG, "nslots differs from the bins' nslots");
+  }
+  const KGrid G = make_kgrid(*grid);
+  const KPart P = make_kpart(*p);
+  const FieldPtrs F{{Ex, Ey, Ez, Bx, By, Bz}};
+  const double h = 0.5 * qm * dt;
+#define PU(O_, D_) launch_push<O_, D_>(G, P, b, F, h, dt, stream)
+  if (G.dim == 3) {
+    if (G.order == 1) PU(1, 3); else if (G.order == 2) PU(2, 3); else PU(3, 3);
+  } else {
+    if (G.order == 1) PU(1, 2); else if (G.order == 2) PU(2, 2); else PU(3, 2);
+  }
+#undef PU
+  if (b) b->movers_fresh = false;
+  return check_hip(hipGetLastError(), "pic_push launch");
 }

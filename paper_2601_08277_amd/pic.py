@@ -19,13 +19,13 @@ PATH_AUTO, PATH_ATOMIC, PATH_CELL_VALU, PATH_MFMA_BF16, PATH_MFMA_FP16, PATH_UNS
 PATH_NAMES = {"auto": PATH_AUTO, "atomic": PATH_ATOMIC, "cell_valu": PATH_CELL_VALU,
               "mfma_bf16": PATH_MFMA_BF16, "mfma_fp16": PATH_MFMA_FP16, "unsorted": PATH_UNSORTED}
 REBIN_FULL, REBIN_INCREMENTAL, REBIN_AUTO = 0, 1, 2
-F_ACCUMULATE, F_DETERMINISTIC, F_EMIT_MOVERS, F_DRIFT = 1, 2, 4, 8
+F_ACCUMULATE, F_DETERMINISTIC, F_EMIT_MOVERS, F_DRIFT, F_MIDPOINT = 1, 2, 4, 8, 16
 INVALID_ID = -1
 
 EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "pic_bins_destroy",
            "pic_bins_get_view", "pic_bins_copy_tables", "pic_rebin", "pic_rebin_stats_read", "pic_bins_report_perf",
            "pic_deposit", "pic_deposit_rho", "pic_gather_fields", "pic_deposit_backward",
-           "pic_drift",
+           "pic_drift", "pic_push",
            "pic_plan_create",
            "pic_plan_destroy", "pic_deposit_batched", "pic_plan_info", "pic_check",
            "pic_last_error"]
@@ -98,6 +98,7 @@ def lib():
     L.pic_deposit_backward.argtypes = [P(PicGrid), P(PicParticles), vp, vp, vp, vp, vp, vp, vp,
                                        vp, vp, vp, vp, u32, vp]
     L.pic_drift.argtypes = [P(PicGrid), P(PicParticles), dbl, vp]
+    L.pic_push.argtypes = [P(PicGrid), P(PicParticles), vp] + [vp] * 6 + [dbl, dbl, u32, vp]
     L.pic_plan_create.argtypes = [P(PicGrid), i32, P(vp), ctypes.c_char_p, P(vp)]
     L.pic_plan_destroy.argtypes = [vp]
     L.pic_deposit_batched.argtypes = [vp, P(PicParticles), P(vp), i32, u32, vp]
@@ -351,6 +352,14 @@ def gather_fields(grid, parts, bins, E, B):
                                    bins.h if bins else None, *[_ptr(f) for f in F],
                                    *[_ptr(o) for o in out], _stream()))
     return out[:3], out[3:]
+
+
+def push(grid, parts, bins, E, B, qm, dt):
+    """Boris push in place (pic_push): gather E, B, rotate u, move x by dt."""
+    F = [f.contiguous() for f in list(E) + list(B)]
+    pc = parts.c()
+    _check(lib().pic_push(ctypes.byref(grid.c), ctypes.byref(pc), bins.h if bins else None,
+                          *[_ptr(f) for f in F], float(qm), float(dt), 0, _stream()))
 
 
 def deposit_backward(grid, parts, bins, G, want_dw=True):
