@@ -10,7 +10,10 @@ shapes   1D B-spline shape factors of order 1..3 on nodal and half-cell (stagger
          positions, their derivatives, and the continuous kernels B_o(t).
 deposit  Eq. 1 of the paper (Sec. 3.1) evaluated directly: per-particle stencil
          scatter, an all-pairs brute-force evaluation, the adjoint (gather) of the
-         deposit, and the constant-velocity drift used between steps.
+         deposit, the constant-velocity drift used between steps, the field gather,
+         the relativistic Boris push and the time-centred (midpoint) current.
+esirkepov  The charge-conserving current of Esirkepov's density decomposition (the
+         scheme the paper lists as unsupported), from old and new positions.
 binning  Cell index of a particle, the cell-sorted binning any correct sorter must
          reproduce (as sets per cell), mover counts, and the global re-sort policy
          of Sec. 4.4.
