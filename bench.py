@@ -180,6 +180,7 @@ def main():
         out["charge_density"] = rho_line(pic, torch, grid, parts, bins, N, ncell)
         out["field_gather"] = gather_line(pic, torch, grid, parts, bins, N, ncell)
         out["midpoint_deposit"] = midpoint_line(pic, torch, grid, parts, bins, N, ncell)
+        out["esirkepov_deposit"] = esirkepov_line(pic, torch, grid, parts, bins, N, ncell)
         # last: the push moves the snapshot's particles
         out["pic_cycle"] = cycle_line(pic, torch, grid, parts, bins, N, ncell)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
@@ -466,6 +467,39 @@ def midpoint_line(pic, torch, grid, parts, bins, N, ncell):
               for c in range(3))
     s_bins.close()
     byts = N * 44 + 3 * ncell * 4
+    return {"particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
+            "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "rel_l2_vs_oracle_32cubed": err}
+
+
+def esirkepov_line(pic, torch, grid, parts, bins, N, ncell):
+    """Charge-conserving current (pic_deposit_esirkepov, order 3) of one drift step of the
+    bench snapshot (dt 0.2), with its rel-L2 against the FP64 oracle on the 32^3 scaled
+    copy."""
+    from oracle import esirkepov as oe
+    from oracle.deposit import OracleGrid
+    old = [parts.x.clone(), parts.y.clone(), parts.z.clone()]
+    pic.drift(grid, parts, grid.c.dt)
+    J = pic.new_J(grid)
+    ms = _events_ms(torch, lambda: pic.deposit_esirkepov(grid, parts, bins, old, J=J), 10)
+    sp, sa, sg, s_parts, s_bins = _c2_small(pic)
+    ids = s_parts.id.cpu().numpy()
+    valid = ids != -1
+    s_old = []
+    for k in ("x", "y", "z"):
+        a = np.zeros(ids.size)
+        a[valid] = sa[k][ids[valid]]
+        s_old.append(torch.from_numpy(a).cuda())
+    pic.drift(sg, s_parts, sp["dt"])
+    got = pic.deposit_esirkepov(sg, s_parts, s_bins, s_old)
+    host = s_parts.to_numpy()
+    order = np.argsort(host["id"][valid])
+    new = [host[k][valid][order] for k in ("x", "y", "z")]
+    want = oe.deposit_esirkepov(OracleGrid.from_params(sp), [sa["x"], sa["y"], sa["z"]], new,
+                                [sa["ux"], sa["uy"], sa["uz"]], sa["w"], sp["dt"])
+    err = max(float(np.linalg.norm(got[c].cpu().numpy() - want[c]) / np.linalg.norm(want[c]))
+              for c in range(3))
+    s_bins.close()
+    byts = N * 56 + 3 * ncell * 4     # old + new positions, weight, id in; J out
     return {"particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
             "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "rel_l2_vs_oracle_32cubed": err}
 

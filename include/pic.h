@@ -129,7 +129,8 @@ typedef struct {
   double empty_slot_ratio;    /* empty slots / slots inside bins                       */
   int32_t global_sort_recommended; /* policy decision after the last rebin (0/1)      */
   int32_t last_mode;          /* PIC_REBIN_FULL or PIC_REBIN_INCREMENTAL as executed  */
-  uint32_t error_flags;       /* bit 0 out of domain, bit 1 non-finite, bit 2 capacity */
+  uint32_t error_flags;       /* bit 0 out of domain, 1 non-finite, 2 capacity, 3 stencil */
+                              /* outside the stored nodes, 4 move of a cell or more     */
 } pic_rebin_stats;
 
 /* Default policy values. */
@@ -248,6 +249,26 @@ pic_status pic_gather_fields(const pic_grid* grid, const pic_particles* p, pic_b
 pic_status pic_push(const pic_grid* grid, pic_particles* p, pic_bins* bins, const float* Ex,
                     const float* Ey, const float* Ez, const float* Bx, const float* By,
                     const float* Bz, double qm, double dt, unsigned flags, hipStream_t stream);
+
+/* Charge-conserving current (Esirkepov's density decomposition, the scheme the paper lists
+ * as unsupported in Sec. 6): for each valid particle moving from (x_old, y_old, z_old) to
+ * its current position in p during grid->dt, J_d on the faces i+1/2 is
+ * -q W dx_d/dt times the running sum along d of W_d, with W_d built from the 1D nodal
+ * weights at the two positions (order grid->order, o+2 nodes per dimension), so that
+ * (rho_new - rho_old)/dt + div J = 0 holds for the charge density of pic_deposit_rho. In
+ * 2D, Jz = q W v_z times the time-averaged weights (v from u). x_old, y_old, z_old: device
+ * float64 arrays of nslots in p's slot order (z_old unused in 2D). Periodic moves take the
+ * nearest image; a move of a cell or more along a dimension is skipped and reported by
+ * pic_check (INVALID_PARTICLE), as are non-finite and out-of-domain positions. Overwrites
+ * J unless PIC_F_ACCUMULATE (the only flag). With bins (filled by pic_rebin, for either
+ * position) each tile accumulates in LDS and adds its window to J with float atomics;
+ * without bins every particle adds its box with float atomics. The order of the atomic
+ * additions varies, so results agree between calls to float32 rounding, not bitwise.
+ * Errors: INVALID_ARG (bad arguments, dt zero or non-finite, bins for another grid). */
+pic_status pic_deposit_esirkepov(const pic_grid* grid, const pic_particles* p, pic_bins* bins,
+                                 const double* x_old, const double* y_old, const double* z_old,
+                                 float* Jx, float* Jy, float* Jz, unsigned flags,
+                                 hipStream_t stream);
 
 /* Constant-velocity move of every valid particle, x += v dt (float64), with periodic
  * wrap: the stand-in for the particle push between steps. */

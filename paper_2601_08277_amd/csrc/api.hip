@@ -502,6 +502,8 @@ extern "C" pic_status pic_check(pic_bins* b, hipStream_t stream) {
   HIP_TRY(hipMemcpy(&err, b->kb.err, sizeof(uint32_t), hipMemcpyDeviceToHost));
   HIP_TRY(hipMemset(b->kb.err, 0, sizeof(uint32_t)));
   if (err & PIC_EF_NONFINITE) return set_error(PIC_ERR_INVALID_PARTICLE, "non-finite particle position");
+  if (err & PIC_EF_MOVE)
+    return set_error(PIC_ERR_INVALID_PARTICLE, "a particle moved a cell or more in one step");
   if (err & (PIC_EF_DOMAIN | PIC_EF_STENCIL)) return set_error(PIC_ERR_OUT_OF_DOMAIN, "particle outside the domain");
   if (err & PIC_EF_CAPACITY) return set_error(PIC_ERR_CAPACITY, "particle arrays too small for the bins");
   return PIC_OK;

@@ -1,0 +1,425 @@
+// Charge-conserving current deposition (Esirkepov's density decomposition).
+//
+// The paper deposits the direct current of Eq. 1 and lists charge-conserving schemes as
+// unsupported (Sec. 6). For a particle moving from grid coordinate xi0 to xi1 within one
+// step (less than a cell per dimension), with 1D nodal B-spline weights S0, S1 on a common
+// box of O+2 nodes per dimension, DS = S1 - S0 and M = (S0 + S1)/2, the published
+// decomposition (Esirkepov, Comput. Phys. Commun. 135 (2001) 144) gives in 3D
+//
+//   Jx(i+1/2, j, k) = A_x(i) * (M_y(j) M_z(k) + DS_y(j) DS_z(k) / 12),
+//   A_x(i) = -q W dx/dt * sum_{i' <= i} DS_x(i'),
+//
+// since S0y S0z + DSy S0z/2 + S0y DSz/2 + DSy DSz/3 = My Mz + DSy DSz/12 (the same holds
+// for y and z by exchange). In 2D, Jx = A_x(i) M_y(j), Jy likewise, and the out-of-plane
+// Jz = q W v_z (Mx My + DSx DSy / 12). So every component is a sum of at most two outer
+// products of short per-particle vectors, which is how the kernels evaluate it.
+//
+// The weights are formed in float64: DS is a difference of two weights close to each
+// other for small moves, and float32 would lose most of its digits there. The factor
+// vectors are then rounded to float32 and the outer products accumulated in float32.
+//
+// Tiled path (bins filled by pic_rebin): one workgroup per tile; wave 3 prepares 64
+// particles at a time (one per lane, float64) into a double-buffered LDS record list;
+// waves 0-2 each own one J component of an LDS window covering the tile plus a margin of
+// ML cells and add each particle's box with lanes = box nodes (plain read-add-write: one
+// particle per instruction touches distinct nodes, and one wave owns each component).
+// Particles whose box does not fit the window are added with global atomics. The window
+// is then added to J with one global atomic per non-zero entry.
+#include <algorithm>
+#include <cmath>
+
+#include "deposit_common.h"
+
+uint32_t* nobins_err_ptr();
+
+namespace {
+
+constexpr int ESK_WAVES = 4;
+constexpr int ESK_CHUNK = PIC_WAVE;
+
+template <int O>
+constexpr int esk_margin() {
+  return (O + 1) / 2 + 2;
+}
+
+// record: [0] window base (int bits), [1] q W v_z (2D), then per dimension M[O+2],
+// DS[O+2], A[O+1]; odd length, so that 64 lanes writing one record each hit distinct banks
+template <int O, int DIM>
+constexpr int esk_rec() {
+  return (2 + DIM * (3 * O + 5)) | 1;
+}
+
+// Box extent of component C along dimension D: O+1 faces along the component's own axis,
+// O+2 nodes across it; in 2D the out-of-plane component has O+2 nodes along x and y.
+template <int O, int DIM, int C, int D>
+constexpr int esk_ext() {
+  return D < DIM ? (D == C ? O + 1 : O + 2) : 1;
+}
+
+template <int O>
+__device__ __forceinline__ double bspline(double t) {
+  const double a = fabs(t);
+  if constexpr (O == 1) {
+    return a < 1.0 ? 1.0 - a : 0.0;
+  } else if constexpr (O == 2) {
+    if (a <= 0.5) return 0.75 - a * a;
+    const double r = 1.5 - a;
+    return a < 1.5 ? 0.5 * r * r : 0.0;
+  } else {
+    if (a <= 1.0) return 2.0 / 3.0 - a * a + 0.5 * a * a * a;
+    const double r = 2.0 - a;
+    return a < 2.0 ? r * r * r / 6.0 : 0.0;
+  }
+}
+
+__device__ __forceinline__ int esk_store(const KGrid& G, int d, int m) {
+  if (G.per[d]) {
+    m %= G.n[d];
+    return m < 0 ? m + G.n[d] : m;
+  }
+  m += G.g[d];
+  return (m >= 0 && m < G.N[d]) ? m : -1;
+}
+
+struct EskWin {
+  int w0[3], W[3], size;
+};
+
+__device__ __forceinline__ EskWin esk_window(const TileBox& tb, int dim, int ml) {
+  EskWin w;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const bool used = d < dim;
+    w.w0[d] = used ? tb.c0[d] - ml : 0;
+    w.W[d] = used ? tb.e[d] + 2 * ml : 1;
+  }
+  w.size = w.W[0] * w.W[1] * w.W[2];
+  return w;
+}
+
+// Factor vectors of slot s into rec (float32) and the box's first node per dimension.
+// Returns false (with an error bit) for a non-finite or out-of-domain position or a move
+// of a cell or more.
+template <int O, int DIM>
+__device__ __forceinline__ bool esk_prep(const KGrid& G, const KPart& P, const double* const* xo,
+                                         double idt, int s, float* rec, int* first,
+                                         uint32_t& bad) {
+  const double xn[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
+  const double qw = (double)G.q * (double)P.w[s];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double a = (xo[d][s] - G.x0[d]) * G.inv_dx[d];
+    const double b0 = (xn[d] - G.x0[d]) * G.inv_dx[d];
+    if (!isfinite(a) || !isfinite(b0)) {
+      bad |= PIC_EF_NONFINITE;
+      return false;
+    }
+    if (!(a >= 0.0 && a <= (double)G.n[d] && b0 >= 0.0 && b0 <= (double)G.n[d])) {
+      bad |= PIC_EF_DOMAIN;
+      return false;
+    }
+    double step = b0 - a;
+    if (G.per[d]) step -= (double)G.n[d] * rint(step / (double)G.n[d]);
+    if (!(fabs(step) < 1.0)) {
+      bad |= PIC_EF_MOVE;
+      return false;
+    }
+    const double b = a + step;
+    const int f = (int)floor(fmin(a, b) - 0.5 * (O + 1)) + 1;
+    first[d] = f;
+    float* M = rec + 2 + d * (3 * O + 5);
+    float* DS = M + (O + 2);
+    float* A = DS + (O + 2);
+    const double scale = -qw * idt / G.inv_dx[d];
+    double run = 0.0;
+#pragma unroll
+    for (int k = 0; k < O + 2; ++k) {
+      const double s0 = bspline<O>((double)(f + k) - a);
+      const double s1 = bspline<O>((double)(f + k) - b);
+      const double ds = s1 - s0;
+      M[k] = (float)(0.5 * (s0 + s1));
+      DS[k] = (float)ds;
+      if (k < O + 1) {
+        run += ds;
+        A[k] = (float)(scale * run);
+      }
+    }
+  }
+  if constexpr (DIM == 2) {
+    const float ux = P.ux[s], uy = P.uy[s], uz = P.uz[s];
+    rec[1] = (float)qw * uz / sqrtf(1.0f + (ux * ux + uy * uy + uz * uz));
+  } else {
+    rec[1] = 0.0f;
+  }
+  return true;
+}
+
+// Value of box task (o0, o1, o2) of component C from a record.
+template <int O, int DIM, int C>
+__device__ __forceinline__ float esk_value(const float* rec, const int* o) {
+  constexpr int RS = 3 * O + 5;
+  const float* base = rec + 2;
+  if constexpr (DIM == 3) {
+    constexpr int D1 = (C + 1) % 3, D2 = (C + 2) % 3;
+    const float a = base[C * RS + 2 * (O + 2) + o[C]];
+    const float m1 = base[D1 * RS + o[D1]], m2 = base[D2 * RS + o[D2]];
+    const float d1 = base[D1 * RS + (O + 2) + o[D1]], d2 = base[D2 * RS + (O + 2) + o[D2]];
+    return a * (m1 * m2 + (1.0f / 12.0f) * (d1 * d2));
+  } else if constexpr (C < 2) {
+    constexpr int D1 = 1 - C;
+    return base[C * RS + 2 * (O + 2) + o[C]] * base[D1 * RS + o[D1]];
+  } else {
+    const float mx = base[o[0]], my = base[RS + o[1]];
+    const float dx = base[(O + 2) + o[0]], dy = base[RS + (O + 2) + o[1]];
+    return rec[1] * (mx * my + (1.0f / 12.0f) * (dx * dy));
+  }
+}
+
+// Component C of one particle's box added to J with global atomics. With REG (a record
+// held in registers) the loops are unrolled so that every index is a compile-time
+// constant; a record in LDS is read with plain loops.
+template <int O, int DIM, int C, bool REG>
+__device__ __forceinline__ void esk_global_comp(const KGrid& G, const float* rec,
+                                                const int* first, float* J, uint32_t& bad) {
+  constexpr int NX = esk_ext<O, DIM, C, 0>(), NY = esk_ext<O, DIM, C, 1>();
+  constexpr int NT = NX * NY * esk_ext<O, DIM, C, 2>();
+#pragma unroll (REG ? NT : 1)
+  for (int t = 0; t < NT; ++t) {
+    const int ox = t % NX, oy = (t / NX) % NY, oz = t / (NX * NY);
+    const int o[3] = {ox, oy, oz};
+    const float v = esk_value<O, DIM, C>(rec, o);
+    const int ix = esk_store(G, 0, first[0] + ox);
+    const int iy = esk_store(G, 1, first[1] + oy);
+    const int iz = DIM == 3 ? esk_store(G, 2, first[2] + oz) : 0;
+    if ((ix | iy | iz) < 0) {
+      if (v != 0.0f) bad |= PIC_EF_STENCIL;
+      continue;
+    }
+    unsafeAtomicAdd(&J[((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
+  }
+}
+
+template <int O, int DIM, bool REG>
+__device__ __forceinline__ void esk_global(const KGrid& G, const float* rec, const int* first,
+                                           float* J0, float* J1, float* J2, uint32_t& bad) {
+  esk_global_comp<O, DIM, 0, REG>(G, rec, first, J0, bad);
+  esk_global_comp<O, DIM, 1, REG>(G, rec, first, J1, bad);
+  esk_global_comp<O, DIM, 2, REG>(G, rec, first, J2, bad);
+}
+
+struct OldPos {
+  const double* p[3];
+};
+
+// One particle per lane, global atomics (no bins).
+template <int O, int DIM>
+__global__ __launch_bounds__(256) void k_esk_global(KGrid G, KPart P, OldPos X, double idt,
+                                                    float* J0, float* J1, float* J2,
+                                                    uint32_t* err) {
+  uint32_t bad = 0;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.nslots; s += gridDim.x * blockDim.x) {
+    if (P.id[s] == PIC_INVALID_ID) continue;
+    float rec[esk_rec<O, DIM>()];
+    int first[3] = {0, 0, 0};
+    if (esk_prep<O, DIM>(G, P, X.p, idt, s, rec, first, bad))
+      esk_global<O, DIM, true>(G, rec, first, J0, J1, J2, bad);
+  }
+  if (bad) atomicOr(err, bad);
+}
+
+template <int O, int DIM>
+struct EskLayout {
+  size_t win_off, rec_off, lst_off, cnt_off, total;
+  __host__ __device__ EskLayout(const int* T, int dim) {
+    size_t ws = 1;
+    for (int d = 0; d < 3; ++d) ws *= (size_t)(d < dim ? T[d] + 2 * esk_margin<O>() : 1);
+    win_off = 0;
+    rec_off = 3 * ws * sizeof(float);
+    lst_off = rec_off + 2 * (size_t)ESK_CHUNK * esk_rec<O, DIM>() * sizeof(float);
+    cnt_off = lst_off + 2 * (size_t)ESK_CHUNK * sizeof(int);
+    total = cnt_off + 2 * sizeof(int);
+  }
+};
+
+// Wave C adds component C of the `n` listed records into its window.
+template <int O, int DIM, int C>
+__device__ __forceinline__ void esk_consume(const float* recs, const int* lst, int n,
+                                            const EskWin& w, float* win) {
+  constexpr int R = esk_rec<O, DIM>();
+  constexpr int sz[3] = {esk_ext<O, DIM, C, 0>(), esk_ext<O, DIM, C, 1>(),
+                         esk_ext<O, DIM, C, 2>()};
+  constexpr int T = sz[0] * sz[1] * sz[2];
+  const int lane = threadIdx.x % PIC_WAVE;
+  float* wc = win + C * w.size;
+  for (int pass = 0; pass * PIC_WAVE < T; ++pass) {
+    const int t = lane + pass * PIC_WAVE;
+    const bool act = t < T;
+    const int o[3] = {t % sz[0], (t / sz[0]) % sz[1], t / (sz[0] * sz[1])};
+    const int loff = (o[2] * w.W[1] + o[1]) * w.W[0] + o[0];
+    for (int p = 0; p < n; ++p) {
+      const float* r = recs + lst[p] * R;
+      if (act) {
+        const int idx = __float_as_int(r[0]) + loff;
+        wc[idx] += esk_value<O, DIM, C>(r, o);
+      }
+    }
+  }
+}
+
+// Producer lane: slot S0 + 64 k + lane prepared into the lane's record of buffer k & 1;
+// records whose box fits the window are listed for the consumers, the others are added to
+// J from here.
+template <int O, int DIM>
+__device__ __forceinline__ void esk_stage(const KGrid& G, const KPart& P, const OldPos& X,
+                                          double idt, const EskWin& w, int S0, int S1, int k,
+                                          float* recs, int* lst, int* cnt, float* J0, float* J1,
+                                          float* J2, uint32_t& bad) {
+  constexpr int R = esk_rec<O, DIM>();
+  const int lane = threadIdx.x % PIC_WAVE;
+  const int s = S0 + k * ESK_CHUNK + lane;
+  float* q = recs + ((k & 1) * ESK_CHUNK + lane) * R;
+  float rec[R];
+  int first[3] = {0, 0, 0};
+  const bool ok = s < S1 && P.id[s] != PIC_INVALID_ID &&
+                  esk_prep<O, DIM>(G, P, X.p, idt, s, rec, first, bad);
+  bool fits = ok;
+  if (ok) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const int r = first[d] - w.w0[d];
+      fits = fits && r >= 0 && r + O + 1 < w.W[d];
+    }
+    const int rz = DIM == 3 ? first[2] - w.w0[2] : 0;
+    rec[0] = __int_as_float((rz * w.W[1] + (first[1] - w.w0[1])) * w.W[0] + (first[0] - w.w0[0]));
+#pragma unroll
+    for (int i = 0; i < R; ++i) q[i] = rec[i];
+  }
+  if (ok && !fits) esk_global<O, DIM, false>(G, q, first, J0, J1, J2, bad);
+  const unsigned long long m = __ballot(fits);
+  const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+  if (fits) lst[(k & 1) * ESK_CHUNK + rank] = lane;
+  if (lane == 0) cnt[k & 1] = (int)__popcll(m);
+}
+
+template <int O, int DIM>
+__global__ __launch_bounds__(ESK_WAVES* PIC_WAVE) void k_esk_tile(KGrid G, KBins B, KPart P,
+                                                                  OldPos X, double idt,
+                                                                  float* J0, float* J1,
+                                                                  float* J2) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int R = esk_rec<O, DIM>();
+  constexpr int ML = esk_margin<O>();
+  const EskLayout<O, DIM> L(B.T, DIM);
+  float* win = (float*)(smem + L.win_off);
+  float* recs = (float*)(smem + L.rec_off);
+  int* lst = (int*)(smem + L.lst_off);
+  int* cnt = (int*)(smem + L.cnt_off);
+  const TileBox tb = tile_box(G.n, B.T, B.nt, blockIdx.x);
+  const EskWin w = esk_window(tb, DIM, ML);
+  const int wave = threadIdx.x / PIC_WAVE;
+  const int lane = threadIdx.x % PIC_WAVE;
+  for (int i = threadIdx.x; i < 3 * w.size; i += blockDim.x) win[i] = 0.0f;
+  const int S0 = B.off[tb.b0], S1 = B.off[tb.b0 + tb.nb];
+  const int nchunk = (S1 - S0 + ESK_CHUNK - 1) / ESK_CHUNK;
+  uint32_t bad = 0;
+  __syncthreads();
+  if (wave == ESK_WAVES - 1) {
+    if (nchunk > 0)
+      esk_stage<O, DIM>(G, P, X, idt, w, S0, S1, 0, recs, lst, cnt, J0, J1, J2, bad);
+    __syncthreads();
+    for (int k = 0; k < nchunk; ++k) {
+      if (k + 1 < nchunk)
+        esk_stage<O, DIM>(G, P, X, idt, w, S0, S1, k + 1, recs, lst, cnt, J0, J1, J2, bad);
+      __syncthreads();
+    }
+  } else {
+    __syncthreads();
+    for (int k = 0; k < nchunk; ++k) {
+      const float* rk = recs + (k & 1) * ESK_CHUNK * R;
+      const int* lk = lst + (k & 1) * ESK_CHUNK;
+      const int n = cnt[k & 1];
+      if (wave == 0) esk_consume<O, DIM, 0>(rk, lk, n, w, win);
+      else if (wave == 1) esk_consume<O, DIM, 1>(rk, lk, n, w, win);
+      else esk_consume<O, DIM, 2>(rk, lk, n, w, win);
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // window -> J, one atomic per non-zero entry
+  for (int i = threadIdx.x; i < 3 * w.size; i += blockDim.x) {
+    const float v = win[i];
+    if (v == 0.0f) continue;
+    const int c = i / w.size;
+    const int r = i - c * w.size;
+    const int W01 = w.W[0] * w.W[1];
+    const int wz = r / W01, wy = (r - wz * W01) / w.W[0], wx = r - wz * W01 - wy * w.W[0];
+    const int ix = esk_store(G, 0, w.w0[0] + wx), iy = esk_store(G, 1, w.w0[1] + wy);
+    const int iz = DIM == 3 ? esk_store(G, 2, w.w0[2] + wz) : 0;
+    if ((ix | iy | iz) < 0) {
+      bad |= PIC_EF_STENCIL;
+      continue;
+    }
+    float* Jc = c == 0 ? J0 : (c == 1 ? J1 : J2);
+    unsafeAtomicAdd(&Jc[((int64_t)iz * G.N[1] + iy) * G.N[0] + ix], v);
+  }
+  if (bad) atomicOr(B.err, bad);
+}
+
+template <int O, int DIM>
+void launch_esk(const KGrid& G, const KPart& P, pic_bins* b, const OldPos& X, double idt,
+                float* J0, float* J1, float* J2, hipStream_t s) {
+  if (b && b->sorted_once) {
+    const EskLayout<O, DIM> L(b->kb.T, DIM);
+    if (L.total <= b->max_lds) {
+      hipLaunchKernelGGL((k_esk_tile<O, DIM>), dim3(b->kb.ntiles), dim3(ESK_WAVES * PIC_WAVE),
+                         L.total, s, G, b->kb, P, X, idt, J0, J1, J2);
+      return;
+    }
+  }
+  const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)P.nslots + 255) / 256, 16384);
+  if (blocks == 0) return;
+  hipLaunchKernelGGL((k_esk_global<O, DIM>), dim3(blocks), dim3(256), 0, s, G, P, X, idt, J0, J1,
+                     J2, b ? b->kb.err : nobins_err_ptr());
+}
+
+}  // namespace
+
+extern "C" pic_status pic_deposit_esirkepov(const pic_grid* grid, const pic_particles* p,
+                                            pic_bins* b, const double* x_old,
+                                            const double* y_old, const double* z_old,
+                                            float* Jx, float* Jy, float* Jz, unsigned flags,
+                                            hipStream_t stream) {
+  pic_status st = validate_grid(grid);
+  if (st != PIC_OK) return st;
+  if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
+  if (!Jx || !Jy || !Jz) return set_error(PIC_ERR_INVALID_ARG, "J pointers must not be NULL");
+  if (p->nslots > 0 && (!x_old || !y_old || (grid->dim == 3 && !z_old)))
+    return set_error(PIC_ERR_INVALID_ARG, "old position pointers must not be NULL");
+  if (flags & ~(unsigned)PIC_F_ACCUMULATE)
+    return set_error(PIC_ERR_INVALID_ARG, "pic_deposit_esirkepov takes PIC_F_ACCUMULATE only");
+  if (!std::isfinite(grid->dt) || grid->dt == 0.0)
+    return set_error(PIC_ERR_INVALID_ARG, "dt must be finite and non-zero");
+  if (b) {
+    if (!same_grid(*grid, b->grid)) return set_error(PIC_ERR_INVALID_ARG, "grid differs from the bins' grid");
+    if (p->nslots != b->nslots) return set_error(PIC_ERR_INVALID_ARG, "nslots differs from the bins' nslots");
+  }
+  const KGrid G = make_kgrid(*grid);
+  const KPart P = make_kpart(*p);
+  const OldPos X{{x_old, y_old, grid->dim == 3 ? z_old : x_old}};
+  const int64_t nJ = (int64_t)G.N[0] * G.N[1] * G.N[2];
+  if (!(flags & PIC_F_ACCUMULATE)) {
+    launch_fill_f32(Jx, nJ, 0.0f, stream);
+    launch_fill_f32(Jy, nJ, 0.0f, stream);
+    launch_fill_f32(Jz, nJ, 0.0f, stream);
+  }
+  const double idt = 1.0 / grid->dt;
+#define ES(O_, D_) launch_esk<O_, D_>(G, P, b, X, idt, Jx, Jy, Jz, stream)
+  if (G.dim == 3) {
+    if (G.order == 1) ES(1, 3); else if (G.order == 2) ES(2, 3); else ES(3, 3);
+  } else {
+    if (G.order == 1) ES(1, 2); else if (G.order == 2) ES(2, 2); else ES(3, 2);
+  }
+#undef ES
+  return check_hip(hipGetLastError(), "pic_deposit_esirkepov launch");
+}

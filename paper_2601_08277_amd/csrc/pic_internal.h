@@ -14,7 +14,8 @@ enum : uint32_t {
   PIC_EF_DOMAIN = 1u,     // a particle's cell lies outside [0, n)
   PIC_EF_NONFINITE = 2u,  // a position is NaN or infinite
   PIC_EF_CAPACITY = 4u,   // a full sort could not fit the bins into the slots
-  PIC_EF_STENCIL = 8u     // a guard-bounded stencil left the stored nodes
+  PIC_EF_STENCIL = 8u,    // a guard-bounded stencil left the stored nodes
+  PIC_EF_MOVE = 16u       // a particle moved a cell or more in one step (charge-conserving)
 };
 
 // Device counters kept in the bins object.

@@ -25,7 +25,7 @@ INVALID_ID = -1
 EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "pic_bins_destroy",
            "pic_bins_get_view", "pic_bins_copy_tables", "pic_rebin", "pic_rebin_stats_read", "pic_bins_report_perf",
            "pic_deposit", "pic_deposit_rho", "pic_gather_fields", "pic_deposit_backward",
-           "pic_drift", "pic_push",
+           "pic_drift", "pic_push", "pic_deposit_esirkepov",
            "pic_plan_create",
            "pic_plan_destroy", "pic_deposit_batched", "pic_plan_info", "pic_check",
            "pic_last_error"]
@@ -99,6 +99,7 @@ def lib():
                                        vp, vp, vp, vp, u32, vp]
     L.pic_drift.argtypes = [P(PicGrid), P(PicParticles), dbl, vp]
     L.pic_push.argtypes = [P(PicGrid), P(PicParticles), vp] + [vp] * 6 + [dbl, dbl, u32, vp]
+    L.pic_deposit_esirkepov.argtypes = [P(PicGrid), P(PicParticles), vp] + [vp] * 6 + [u32, vp]
     L.pic_plan_create.argtypes = [P(PicGrid), i32, P(vp), ctypes.c_char_p, P(vp)]
     L.pic_plan_destroy.argtypes = [vp]
     L.pic_deposit_batched.argtypes = [vp, P(PicParticles), P(vp), i32, u32, vp]
@@ -360,6 +361,19 @@ def push(grid, parts, bins, E, B, qm, dt):
     pc = parts.c()
     _check(lib().pic_push(ctypes.byref(grid.c), ctypes.byref(pc), bins.h if bins else None,
                           *[_ptr(f) for f in F], float(qm), float(dt), 0, _stream()))
+
+
+def deposit_esirkepov(grid, parts, bins, old, flags=0, J=None):
+    """Charge-conserving current (pic_deposit_esirkepov) of the move from `old` (three
+    float64 tensors in slot order) to the particles' current positions in grid.dt."""
+    if J is None:
+        J = new_J(grid)
+    oc = [o.contiguous() for o in old]
+    pc = parts.c()
+    _check(lib().pic_deposit_esirkepov(ctypes.byref(grid.c), ctypes.byref(pc),
+                                       bins.h if bins else None, *[_ptr(o) for o in oc],
+                                       _ptr(J[0]), _ptr(J[1]), _ptr(J[2]), flags, _stream()))
+    return J
 
 
 def deposit_backward(grid, parts, bins, G, want_dw=True):
