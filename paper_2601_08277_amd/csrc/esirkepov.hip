@@ -243,8 +243,9 @@ struct EskLayout {
 
 // Wave C adds component C of the `n` listed records into its window.
 template <int O, int DIM, int C>
-__device__ __forceinline__ void esk_consume(const float* recs, const int* lst, int n,
-                                            const EskWin& w, float* win) {
+__device__ __forceinline__ void esk_consume(const float* __restrict__ recs,
+                                            const int* __restrict__ lst, int n,
+                                            const EskWin& w, float* __restrict__ win) {
   constexpr int R = esk_rec<O, DIM>();
   constexpr int sz[3] = {esk_ext<O, DIM, C, 0>(), esk_ext<O, DIM, C, 1>(),
                          esk_ext<O, DIM, C, 2>()};
@@ -256,6 +257,7 @@ __device__ __forceinline__ void esk_consume(const float* recs, const int* lst, i
     const bool act = t < T;
     const int o[3] = {t % sz[0], (t / sz[0]) % sz[1], t / (sz[0] * sz[1])};
     const int loff = (o[2] * w.W[1] + o[1]) * w.W[0] + o[0];
+#pragma unroll 4
     for (int p = 0; p < n; ++p) {
       const float* r = recs + lst[p] * R;
       if (act) {
