@@ -94,3 +94,59 @@ def test_argument_errors_without_gpu(L):
     st = L.pic_bins_create(ctypes.byref(g), t, 0.25, 100, 0, ctypes.byref(h))
     assert st == -1 and b"ng" in L.pic_last_error()
     assert L.pic_deposit(None, None, None, None, None, None, 0, 0, None) == -1
+
+
+def _grid3(pic, order=3, dt=0.5):
+    g = pic.PicGrid()
+    g.dim = 3
+    for d in range(3):
+        g.n[d] = 8
+        g.dx[d] = 1.0
+        g.inv_dx[d] = 1.0
+        g.bc[d] = 0
+    g.order = order
+    g.q = -1.0
+    g.dt = dt
+    return g
+
+
+def _fake_particles(pic, n=16):
+    """Descriptor with non-NULL but never-dereferenced pointers: every check below fails
+    before anything is launched."""
+    p = pic.PicParticles()
+    p.nslots = n
+    for name in ("x", "y", "z", "ux", "uy", "uz", "w", "id"):
+        setattr(p, name, 4096)
+    return p
+
+
+def test_argument_errors_of_the_next_rows_without_gpu(L):
+    from paper_2601_08277_amd import pic
+    g = _grid3(pic)
+    p = _fake_particles(pic)
+    f = ctypes.c_void_p(4096)
+    # push: flags must be 0, qm and dt finite
+    assert L.pic_push(ctypes.byref(g), ctypes.byref(p), None, *[f] * 6, -1.0, 0.2, 1, None) == -1
+    assert b"flags" in L.pic_last_error()
+    assert L.pic_push(ctypes.byref(g), ctypes.byref(p), None, *[f] * 6, float("nan"), 0.2, 0,
+                      None) == -1
+    assert L.pic_push(ctypes.byref(g), ctypes.byref(p), None, None, *[f] * 5, -1.0, 0.2, 0,
+                      None) == -1
+    # Esirkepov: dt must be non-zero, ACCUMULATE is the only flag, old positions needed
+    g0 = _grid3(pic, dt=0.0)
+    assert L.pic_deposit_esirkepov(ctypes.byref(g0), ctypes.byref(p), None, f, f, f, f, f, f, 0,
+                                   None) == -1
+    assert b"dt" in L.pic_last_error()
+    assert L.pic_deposit_esirkepov(ctypes.byref(g), ctypes.byref(p), None, f, f, f, f, f, f,
+                                   pic.F_DRIFT, None) == -1
+    assert L.pic_deposit_esirkepov(ctypes.byref(g), ctypes.byref(p), None, None, f, f, f, f, f,
+                                   0, None) == -1
+    assert b"old" in L.pic_last_error()
+    # midpoint: refused on the tile-atomic and MFMA paths before bins are looked at
+    for path in (pic.PATH_NAMES["atomic"], pic.PATH_NAMES["mfma_bf16"]):
+        assert L.pic_deposit(ctypes.byref(g), ctypes.byref(p), None, f, f, f, path,
+                             pic.F_MIDPOINT, None) == pic.PIC_ERR_UNSUPPORTED
+    # charge density takes ACCUMULATE only; gather needs every pointer
+    assert L.pic_deposit_rho(ctypes.byref(g), ctypes.byref(p), None, f, pic.F_DRIFT, None) == -1
+    assert L.pic_gather_fields(ctypes.byref(g), ctypes.byref(p), None, *[f] * 11, None,
+                               None) == -1
