@@ -56,19 +56,47 @@ constexpr int esk_ext() {
   return D < DIM ? (D == C ? O + 1 : O + 2) : 1;
 }
 
+// Nodal B-spline weights of order O at grid coordinate xi (float64): the O+1 non-zero
+// weights, first at node `start`. Order 1: start = floor(xi), weights 1-f, f. Order 2:
+// m = floor(xi + 1/2), d = xi - m, start = m - 1, weights (1/2 - d)^2/2, 3/4 - d^2,
+// (1/2 + d)^2/2. Order 3: start = floor(xi) - 1, weights (1-f)^3/6, (3f^3 - 6f^2 + 4)/6,
+// (-3f^3 + 3f^2 + 3f + 1)/6, f^3/6.
 template <int O>
-__device__ __forceinline__ double bspline(double t) {
-  const double a = fabs(t);
+__device__ __forceinline__ int nodal_weights(double xi, double* w) {
   if constexpr (O == 1) {
-    return a < 1.0 ? 1.0 - a : 0.0;
+    const double i = floor(xi), f = xi - i;
+    w[0] = 1.0 - f;
+    w[1] = f;
+    return (int)i;
   } else if constexpr (O == 2) {
-    if (a <= 0.5) return 0.75 - a * a;
-    const double r = 1.5 - a;
-    return a < 1.5 ? 0.5 * r * r : 0.0;
+    const double m = floor(xi + 0.5), d = xi - m;
+    const double l = 0.5 - d, r = 0.5 + d;
+    w[0] = 0.5 * (l * l);
+    w[1] = 0.75 - d * d;
+    w[2] = 0.5 * (r * r);
+    return (int)m - 1;
   } else {
-    if (a <= 1.0) return 2.0 / 3.0 - a * a + 0.5 * a * a * a;
-    const double r = 2.0 - a;
-    return a < 2.0 ? r * r * r / 6.0 : 0.0;
+    const double i = floor(xi), f = xi - i, g = 1.0 - f;
+    const double f2 = f * f, f3 = f2 * f;
+    constexpr double s6 = 1.0 / 6.0;
+    w[0] = s6 * (g * g * g);
+    w[1] = s6 * (3.0 * f3 - 6.0 * f2 + 4.0);
+    w[2] = s6 * (-3.0 * f3 + 3.0 * f2 + 3.0 * f + 1.0);
+    w[3] = s6 * f3;
+    return (int)i - 1;
+  }
+}
+
+// The O+1 weights of a stencil starting at `start` on the (O+2)-node box starting at
+// `first` (start - first is 0 or 1).
+template <int O>
+__device__ __forceinline__ void on_box(int start, int first, const double* w, double* box) {
+  const bool shifted = start != first;
+#pragma unroll
+  for (int j = 0; j < O + 2; ++j) {
+    const double lo = j <= O ? w[j] : 0.0;
+    const double hi = j >= 1 ? w[j - 1] : 0.0;
+    box[j] = shifted ? hi : lo;
   }
 }
 
@@ -97,47 +125,82 @@ __device__ __forceinline__ EskWin esk_window(const TileBox& tb, int dim, int ml)
   return w;
 }
 
-// Factor vectors of slot s into rec (float32) and the box's first node per dimension.
-// Returns false (with an error bit) for a non-finite or out-of-domain position or a move
-// of a cell or more.
+struct EskArgs {
+  const double* xo[3];   // positions before the move, slot order
+  double sc[3];          // dx_d / dt
+};
+
+// One slot's inputs, loaded ahead of their use.
+struct EskRaw {
+  double xo[3], xn[3];
+  float w, uz, ux, uy;
+  bool valid;
+};
+
+template <int DIM>
+__device__ __forceinline__ void esk_fetch(const KPart& P, const EskArgs& X, int s, bool in,
+                                          EskRaw& r) {
+  r.valid = in && P.id[s] != PIC_INVALID_ID;
+  if (!r.valid) return;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r.xo[d] = d < DIM ? X.xo[d][s] : 0.0;
+  r.xn[0] = P.x[s];
+  r.xn[1] = P.y[s];
+  r.xn[2] = DIM == 3 ? P.z[s] : 0.0;
+  r.w = P.w[s];
+  if constexpr (DIM == 2) {
+    r.ux = P.ux[s];
+    r.uy = P.uy[s];
+    r.uz = P.uz[s];
+  }
+}
+
+// Factor vectors of one particle into rec (float32) and the box's first node per
+// dimension. Returns false (with an error bit) for a non-finite or out-of-domain position
+// or a move of a cell or more.
 template <int O, int DIM>
-__device__ __forceinline__ bool esk_prep(const KGrid& G, const KPart& P, const double* const* xo,
-                                         double idt, int s, float* rec, int* first,
-                                         uint32_t& bad) {
-  const double xn[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
-  const double qw = (double)G.q * (double)P.w[s];
+__device__ __forceinline__ bool esk_prep(const KGrid& G, const EskArgs& X, const EskRaw& raw,
+                                         float* rec, int* first, uint32_t& bad) {
+  const double qw = (double)G.q * (double)raw.w;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    const double a = (xo[d][s] - G.x0[d]) * G.inv_dx[d];
-    const double b0 = (xn[d] - G.x0[d]) * G.inv_dx[d];
+    const double a = (raw.xo[d] - G.x0[d]) * G.inv_dx[d];
+    const double b0 = (raw.xn[d] - G.x0[d]) * G.inv_dx[d];
     if (!isfinite(a) || !isfinite(b0)) {
       bad |= PIC_EF_NONFINITE;
       return false;
     }
-    if (!(a >= 0.0 && a <= (double)G.n[d] && b0 >= 0.0 && b0 <= (double)G.n[d])) {
+    const double n = (double)G.n[d];
+    if (!(a >= 0.0 && a <= n && b0 >= 0.0 && b0 <= n)) {
       bad |= PIC_EF_DOMAIN;
       return false;
     }
     double step = b0 - a;
-    if (G.per[d]) step -= (double)G.n[d] * rint(step / (double)G.n[d]);
+    if (G.per[d]) {            // nearest periodic image (|step| < n)
+      if (step > 0.5 * n) step -= n;
+      else if (step < -0.5 * n) step += n;
+    }
     if (!(fabs(step) < 1.0)) {
       bad |= PIC_EF_MOVE;
       return false;
     }
     const double b = a + step;
-    const int f = (int)floor(fmin(a, b) - 0.5 * (O + 1)) + 1;
+    double w0[O + 1], w1[O + 1], s0[O + 2], s1[O + 2];
+    const int st0 = nodal_weights<O>(a, w0);
+    const int st1 = nodal_weights<O>(b, w1);
+    const int f = min(st0, st1);
     first[d] = f;
+    on_box<O>(st0, f, w0, s0);
+    on_box<O>(st1, f, w1, s1);
     float* M = rec + 2 + d * (3 * O + 5);
     float* DS = M + (O + 2);
     float* A = DS + (O + 2);
-    const double scale = -qw * idt / G.inv_dx[d];
+    const double scale = -qw * X.sc[d];
     double run = 0.0;
 #pragma unroll
     for (int k = 0; k < O + 2; ++k) {
-      const double s0 = bspline<O>((double)(f + k) - a);
-      const double s1 = bspline<O>((double)(f + k) - b);
-      const double ds = s1 - s0;
-      M[k] = (float)(0.5 * (s0 + s1));
+      const double ds = s1[k] - s0[k];
+      M[k] = (float)(0.5 * (s0[k] + s1[k]));
       DS[k] = (float)ds;
       if (k < O + 1) {
         run += ds;
@@ -146,7 +209,7 @@ __device__ __forceinline__ bool esk_prep(const KGrid& G, const KPart& P, const d
     }
   }
   if constexpr (DIM == 2) {
-    const float ux = P.ux[s], uy = P.uy[s], uz = P.uz[s];
+    const float ux = raw.ux, uy = raw.uy, uz = raw.uz;
     rec[1] = (float)qw * uz / sqrtf(1.0f + (ux * ux + uy * uy + uz * uz));
   } else {
     rec[1] = 0.0f;
@@ -207,21 +270,18 @@ __device__ __forceinline__ void esk_global(const KGrid& G, const float* rec, con
   esk_global_comp<O, DIM, 2, REG>(G, rec, first, J2, bad);
 }
 
-struct OldPos {
-  const double* p[3];
-};
-
 // One particle per lane, global atomics (no bins).
 template <int O, int DIM>
-__global__ __launch_bounds__(256) void k_esk_global(KGrid G, KPart P, OldPos X, double idt,
-                                                    float* J0, float* J1, float* J2,
-                                                    uint32_t* err) {
+__global__ __launch_bounds__(256) void k_esk_global(KGrid G, KPart P, EskArgs X, float* J0,
+                                                    float* J1, float* J2, uint32_t* err) {
   uint32_t bad = 0;
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < P.nslots; s += gridDim.x * blockDim.x) {
-    if (P.id[s] == PIC_INVALID_ID) continue;
+    EskRaw raw;
+    esk_fetch<DIM>(P, X, s, true, raw);
+    if (!raw.valid) continue;
     float rec[esk_rec<O, DIM>()];
     int first[3] = {0, 0, 0};
-    if (esk_prep<O, DIM>(G, P, X.p, idt, s, rec, first, bad))
+    if (esk_prep<O, DIM>(G, X, raw, rec, first, bad))
       esk_global<O, DIM, true>(G, rec, first, J0, J1, J2, bad);
   }
   if (bad) atomicOr(err, bad);
@@ -268,22 +328,20 @@ __device__ __forceinline__ void esk_consume(const float* __restrict__ recs,
   }
 }
 
-// Producer lane: slot S0 + 64 k + lane prepared into the lane's record of buffer k & 1;
-// records whose box fits the window are listed for the consumers, the others are added to
-// J from here.
+// Producer lane: the particle of slot S0 + 64 k + lane (already fetched into raw) prepared
+// into the lane's record of buffer k & 1; records whose box fits the window are listed for
+// the consumers, the others are added to J from here.
 template <int O, int DIM>
-__device__ __forceinline__ void esk_stage(const KGrid& G, const KPart& P, const OldPos& X,
-                                          double idt, const EskWin& w, int S0, int S1, int k,
-                                          float* recs, int* lst, int* cnt, float* J0, float* J1,
-                                          float* J2, uint32_t& bad) {
+__device__ __forceinline__ void esk_stage(const KGrid& G, const EskArgs& X, const EskRaw& raw,
+                                          const EskWin& w, int k, float* recs, int* lst,
+                                          int* cnt, float* J0, float* J1, float* J2,
+                                          uint32_t& bad) {
   constexpr int R = esk_rec<O, DIM>();
   const int lane = threadIdx.x % PIC_WAVE;
-  const int s = S0 + k * ESK_CHUNK + lane;
   float* q = recs + ((k & 1) * ESK_CHUNK + lane) * R;
   float rec[R];
   int first[3] = {0, 0, 0};
-  const bool ok = s < S1 && P.id[s] != PIC_INVALID_ID &&
-                  esk_prep<O, DIM>(G, P, X.p, idt, s, rec, first, bad);
+  const bool ok = raw.valid && esk_prep<O, DIM>(G, X, raw, rec, first, bad);
   bool fits = ok;
   if (ok) {
 #pragma unroll
@@ -306,9 +364,8 @@ __device__ __forceinline__ void esk_stage(const KGrid& G, const KPart& P, const 
 
 template <int O, int DIM>
 __global__ __launch_bounds__(ESK_WAVES* PIC_WAVE) void k_esk_tile(KGrid G, KBins B, KPart P,
-                                                                  OldPos X, double idt,
-                                                                  float* J0, float* J1,
-                                                                  float* J2) {
+                                                                  EskArgs X, float* J0,
+                                                                  float* J1, float* J2) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int R = esk_rec<O, DIM>();
   constexpr int ML = esk_margin<O>();
@@ -327,12 +384,19 @@ __global__ __launch_bounds__(ESK_WAVES* PIC_WAVE) void k_esk_tile(KGrid G, KBins
   uint32_t bad = 0;
   __syncthreads();
   if (wave == ESK_WAVES - 1) {
-    if (nchunk > 0)
-      esk_stage<O, DIM>(G, P, X, idt, w, S0, S1, 0, recs, lst, cnt, J0, J1, J2, bad);
+    // the next chunk's loads are in flight while the current one is prepared
+    EskRaw cur, nxt;
+    esk_fetch<DIM>(P, X, S0 + lane, S0 + lane < S1, cur);
+    esk_fetch<DIM>(P, X, S0 + ESK_CHUNK + lane, S0 + ESK_CHUNK + lane < S1, nxt);
+    if (nchunk > 0) esk_stage<O, DIM>(G, X, cur, w, 0, recs, lst, cnt, J0, J1, J2, bad);
     __syncthreads();
     for (int k = 0; k < nchunk; ++k) {
-      if (k + 1 < nchunk)
-        esk_stage<O, DIM>(G, P, X, idt, w, S0, S1, k + 1, recs, lst, cnt, J0, J1, J2, bad);
+      if (k + 1 < nchunk) {
+        cur = nxt;
+        const int s2 = S0 + (k + 2) * ESK_CHUNK + lane;
+        esk_fetch<DIM>(P, X, s2, s2 < S1, nxt);
+        esk_stage<O, DIM>(G, X, cur, w, k + 1, recs, lst, cnt, J0, J1, J2, bad);
+      }
       __syncthreads();
     }
   } else {
@@ -369,20 +433,20 @@ __global__ __launch_bounds__(ESK_WAVES* PIC_WAVE) void k_esk_tile(KGrid G, KBins
 }
 
 template <int O, int DIM>
-void launch_esk(const KGrid& G, const KPart& P, pic_bins* b, const OldPos& X, double idt,
-                float* J0, float* J1, float* J2, hipStream_t s) {
+void launch_esk(const KGrid& G, const KPart& P, pic_bins* b, const EskArgs& X, float* J0,
+                float* J1, float* J2, hipStream_t s) {
   if (b && b->sorted_once) {
     const EskLayout<O, DIM> L(b->kb.T, DIM);
     if (L.total <= b->max_lds) {
       hipLaunchKernelGGL((k_esk_tile<O, DIM>), dim3(b->kb.ntiles), dim3(ESK_WAVES * PIC_WAVE),
-                         L.total, s, G, b->kb, P, X, idt, J0, J1, J2);
+                         L.total, s, G, b->kb, P, X, J0, J1, J2);
       return;
     }
   }
   const unsigned blocks = (unsigned)std::min<int64_t>(((int64_t)P.nslots + 255) / 256, 16384);
   if (blocks == 0) return;
-  hipLaunchKernelGGL((k_esk_global<O, DIM>), dim3(blocks), dim3(256), 0, s, G, P, X, idt, J0, J1,
-                     J2, b ? b->kb.err : nobins_err_ptr());
+  hipLaunchKernelGGL((k_esk_global<O, DIM>), dim3(blocks), dim3(256), 0, s, G, P, X, J0, J1, J2,
+                     b ? b->kb.err : nobins_err_ptr());
 }
 
 }  // namespace
@@ -408,15 +472,15 @@ extern "C" pic_status pic_deposit_esirkepov(const pic_grid* grid, const pic_part
   }
   const KGrid G = make_kgrid(*grid);
   const KPart P = make_kpart(*p);
-  const OldPos X{{x_old, y_old, grid->dim == 3 ? z_old : x_old}};
+  EskArgs X{{x_old, y_old, grid->dim == 3 ? z_old : x_old}, {0.0, 0.0, 0.0}};
+  for (int d = 0; d < grid->dim; ++d) X.sc[d] = grid->dx[d] / grid->dt;
   const int64_t nJ = (int64_t)G.N[0] * G.N[1] * G.N[2];
   if (!(flags & PIC_F_ACCUMULATE)) {
     launch_fill_f32(Jx, nJ, 0.0f, stream);
     launch_fill_f32(Jy, nJ, 0.0f, stream);
     launch_fill_f32(Jz, nJ, 0.0f, stream);
   }
-  const double idt = 1.0 / grid->dt;
-#define ES(O_, D_) launch_esk<O_, D_>(G, P, b, X, idt, Jx, Jy, Jz, stream)
+#define ES(O_, D_) launch_esk<O_, D_>(G, P, b, X, Jx, Jy, Jz, stream)
   if (G.dim == 3) {
     if (G.order == 1) ES(1, 3); else if (G.order == 2) ES(2, 3); else ES(3, 3);
   } else {
