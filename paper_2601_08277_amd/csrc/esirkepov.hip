@@ -109,9 +109,23 @@ __device__ __forceinline__ int esk_store(const KGrid& G, int d, int m) {
   return (m >= 0 && m < G.N[d]) ? m : -1;
 }
 
+// Window of one component in LDS: W nodes per dimension from w0, stored with row pitch py
+// and plane pitch pz. The pitches are padded to py = 20 and pz = 4 (mod 32), so that the
+// 64 box nodes one consumer instruction touches fall into distinct LDS banks (x
+// component) or at most two to a bank (y, z).
 struct EskWin {
-  int w0[3], W[3], size;
+  int w0[3], W[3], py, pz, size;
 };
+
+__host__ __device__ __forceinline__ int esk_pitch(int need, int residue) {
+  return need + (((residue - need) % 32) + 32) % 32;
+}
+
+__host__ __device__ __forceinline__ size_t esk_win_size(const int* W) {
+  const int py = esk_pitch(W[0], 20);
+  const int pz = esk_pitch(py * W[1], 4);
+  return (size_t)pz * W[2];
+}
 
 __device__ __forceinline__ EskWin esk_window(const TileBox& tb, int dim, int ml) {
   EskWin w;
@@ -121,7 +135,9 @@ __device__ __forceinline__ EskWin esk_window(const TileBox& tb, int dim, int ml)
     w.w0[d] = used ? tb.c0[d] - ml : 0;
     w.W[d] = used ? tb.e[d] + 2 * ml : 1;
   }
-  w.size = w.W[0] * w.W[1] * w.W[2];
+  w.py = esk_pitch(w.W[0], 20);
+  w.pz = esk_pitch(w.py * w.W[1], 4);
+  w.size = w.pz * w.W[2];
   return w;
 }
 
@@ -291,8 +307,9 @@ template <int O, int DIM>
 struct EskLayout {
   size_t win_off, rec_off, lst_off, cnt_off, total;
   __host__ __device__ EskLayout(const int* T, int dim) {
-    size_t ws = 1;
-    for (int d = 0; d < 3; ++d) ws *= (size_t)(d < dim ? T[d] + 2 * esk_margin<O>() : 1);
+    int Wm[3];
+    for (int d = 0; d < 3; ++d) Wm[d] = d < dim ? T[d] + 2 * esk_margin<O>() : 1;
+    const size_t ws = esk_win_size(Wm);
     win_off = 0;
     rec_off = 3 * ws * sizeof(float);
     lst_off = rec_off + 2 * (size_t)ESK_CHUNK * esk_rec<O, DIM>() * sizeof(float);
@@ -316,7 +333,7 @@ __device__ __forceinline__ void esk_consume(const float* __restrict__ recs,
     const int t = lane + pass * PIC_WAVE;
     const bool act = t < T;
     const int o[3] = {t % sz[0], (t / sz[0]) % sz[1], t / (sz[0] * sz[1])};
-    const int loff = (o[2] * w.W[1] + o[1]) * w.W[0] + o[0];
+    const int loff = o[2] * w.pz + o[1] * w.py + o[0];
 #pragma unroll 4
     for (int p = 0; p < n; ++p) {
       const float* r = recs + lst[p] * R;
@@ -350,7 +367,7 @@ __device__ __forceinline__ void esk_stage(const KGrid& G, const EskArgs& X, cons
       fits = fits && r >= 0 && r + O + 1 < w.W[d];
     }
     const int rz = DIM == 3 ? first[2] - w.w0[2] : 0;
-    rec[0] = __int_as_float((rz * w.W[1] + (first[1] - w.w0[1])) * w.W[0] + (first[0] - w.w0[0]));
+    rec[0] = __int_as_float(rz * w.pz + (first[1] - w.w0[1]) * w.py + (first[0] - w.w0[0]));
 #pragma unroll
     for (int i = 0; i < R; ++i) q[i] = rec[i];
   }
@@ -418,8 +435,8 @@ __global__ __launch_bounds__(ESK_WAVES* PIC_WAVE) void k_esk_tile(KGrid G, KBins
     if (v == 0.0f) continue;
     const int c = i / w.size;
     const int r = i - c * w.size;
-    const int W01 = w.W[0] * w.W[1];
-    const int wz = r / W01, wy = (r - wz * W01) / w.W[0], wx = r - wz * W01 - wy * w.W[0];
+    const int wz = r / w.pz, wy = (r - wz * w.pz) / w.py, wx = r - wz * w.pz - wy * w.py;
+    if (wx >= w.W[0] || wy >= w.W[1]) continue;   // padding
     const int ix = esk_store(G, 0, w.w0[0] + wx), iy = esk_store(G, 1, w.w0[1] + wy);
     const int iz = DIM == 3 ? esk_store(G, 2, w.w0[2] + wz) : 0;
     if ((ix | iy | iz) < 0) {
