@@ -395,17 +395,22 @@ __global__ __launch_bounds__(256) void k_insert(KBins B, KPart P, const int32_t*
     const int k = atomicAdd(&B.ins_cnt[nb], 1);
     const int pos = B.len[nb] + k;
     const int cap = B.off[nb + 1] - B.off[nb];
-    if (pos < cap) {
+    const bool fits = pos < cap;
+    if (fits) {
       copy_slot(P, B.off[nb] + pos, P, s);
       P.id[s] = PIC_INVALID_ID;
       P.w[s] = 0.0f;
       atomicAdd(&B.moved_out[ob], 1);
     } else {
-      atomicAdd(&B.ctr[CTR_NOVF], 1);
       int c = bin_cell[nb];
       int i = c % nx, j = (c / nx) % ny, kk = c / (nx * ny);
       atomicAdd(&B.tile_flag[tile_of_cell(B.T, B.nt, i, j, kk)], 1);
     }
+    // one atomic per wave on the shared overflow counter (tens of thousands of
+    // same-address atomics per step would serialise in the L2)
+    const unsigned long long m = __ballot(!fits);
+    if (m && __lane_id() == __ffsll((long long)m) - 1)
+      atomicAdd(&B.ctr[CTR_NOVF], (int)__popcll(m));
   }
 }
 
