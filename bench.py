@@ -179,6 +179,7 @@ def main():
         out["paths"] = path_table(pic, torch, grid, parts, bins, N, ncell)
         out["charge_density"] = rho_line(pic, torch, grid, parts, bins, N, ncell)
         out["field_gather"] = gather_line(pic, torch, grid, parts, bins, N, ncell)
+        out["ablations"] = ablation_lines(pic, torch, grid, parts, bins, N, ncell)
         out["midpoint_deposit"] = midpoint_line(pic, torch, grid, parts, bins, N, ncell)
         out["esirkepov_deposit"] = esirkepov_line(pic, torch, grid, parts, bins, N, ncell)
         # last: the push moves the snapshot's particles
@@ -450,6 +451,29 @@ def _c2_small(pic):
     return sp, sa, sg, s_parts, s_bins
 
 
+def ablation_lines(pic, torch, grid, parts, bins, N, ncell):
+    """The two ablations of the paper's breakdown on the bench snapshot: a global counting
+    sort every step instead of the incremental rebin (deposit with drift + FULL rebin), and
+    deposition of the same particles in shuffled slot order without bins (global atomics,
+    no sort at all)."""
+    J = pic.new_J(grid)
+
+    def full_step():
+        pic.deposit(grid, parts, bins, "auto", pic.F_DRIFT, J=J)
+        pic.rebin(grid, parts, bins, pic.REBIN_FULL)
+
+    full_ms = _events_ms(torch, full_step, 5)
+    g = torch.Generator(device="cuda").manual_seed(31)
+    perm = torch.randperm(parts.nslots, generator=g, device="cuda")
+    sh = pic.Particles(parts.nslots)
+    for name, _ in pic.Particles.FIELDS:
+        getattr(sh, name).copy_(getattr(parts, name)[perm])
+    uns_ms = _events_ms(torch, lambda: pic.deposit(grid, sh, None, "unsorted", J=J), 3)
+    del sh
+    return {"global_sort_every_step": {"ms_per_step": full_ms, "particles_per_s": N / (full_ms * 1e-3)},
+            "shuffled_unsorted_deposit": {"kernel_ms": uns_ms, "particles_per_s": N / (uns_ms * 1e-3)}}
+
+
 def midpoint_line(pic, torch, grid, parts, bins, N, ncell):
     """Time-centred current (PIC_F_MIDPOINT, positions already pushed: deposit at
     x - v dt/2) on the bench snapshot, with its rel-L2 against the FP64 oracle on the 32^3
@@ -565,6 +589,17 @@ def copy_bandwidth(torch):
     return 2 * src.numel() * 4 / (ms * 1e-3) / 1e9
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sample):
     """The FP64 oracle (as written, untuned) on the first `sample` particles of the
     workload, one process on the host."""
@@ -582,7 +617,7 @@ def cpu_baseline(sample):
     return {"value": sample / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
             "sample": f"first {sample} particles of the 128^3 x 8 workload, full grid, "
                       f"FP64 NumPy stencil oracle, one process ({dt:.1f} s)",
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 if __name__ == "__main__":
