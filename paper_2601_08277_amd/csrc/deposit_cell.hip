@@ -63,6 +63,13 @@ constexpr int CV_STALE = 128;   // stale particles a tile keeps for the end phas
 template <int O, int DIM>
 constexpr float CV_AMP_SCALE = O == 3 ? (DIM == 3 ? 1.0f / 216.0f : 1.0f / 36.0f) : 1.0f;
 
+// Position of staged particle q in a stage array. The consumers read one particle per
+// lane at q = (cell start) + k, so with a uniform count of n particles per cell the lanes'
+// addresses are n words apart, and n = 8 would put every fourth lane in one LDS bank.
+// Flipping the low three bits of q with bits 5-7 (a permutation of each 256-word block)
+// spreads such strides over all banks; consecutive q stay conflict-free for the producer.
+__device__ __forceinline__ int cv_sw(int q) { return q ^ ((q >> 5) & 7); }
+
 // A particle found in the bin of another cell, kept for the end phase.
 struct StaleRec {
   int cell[3];
@@ -313,8 +320,8 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
       if (r.lc >= 0) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          sf[d * CV_CAP + r.si] = mine ? p.f[d] : 0.0f;
-          sa[d * CV_CAP + r.si] = mine ? p.amp[d] * CV_AMP_SCALE<O, DIM> : 0.0f;
+          sf[d * CV_CAP + cv_sw(r.si)] = mine ? p.f[d] : 0.0f;
+          sa[d * CV_CAP + cv_sw(r.si)] = mine ? p.amp[d] * CV_AMP_SCALE<O, DIM> : 0.0f;
         }
       }
     }
@@ -343,7 +350,7 @@ __device__ __forceinline__ void cv_accumulate(int k0, int k1, const float* sf, c
   const int nmax = wave_max(n);
   for (int k = 0; k < nmax; ++k) {
     const bool act = k < n;
-    const int q = act ? first + k * STEP : 0;
+    const int q = cv_sw(act ? first + k * STEP : 0);
     float f[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) f[d] = sf[d * CV_CAP + q];
