@@ -61,41 +61,6 @@ struct TileWin {
   }
 };
 
-// Window of a slab of the tile: planes [s0, s1) along the slowest used dimension
-// (z in 3D, y in 2D), full extent along the others. A wave that owns a slab accumulates
-// into its own sub-window, so waves never write the same LDS words.
-template <int O, int DIM>
-struct SubWin {
-  static constexpr int SD = DIM - 1;
-  int o[3];
-  int W[3];
-  int size;
-  int s0;
-  __device__ __forceinline__ SubWin(const TileWin<O, DIM>& tw, int s0_, int s1_) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      o[d] = tw.o[d];
-      W[d] = tw.W[d];
-    }
-    s0 = s0_;
-    o[SD] = tw.c0[SD] + s0_ + TileWin<O, DIM>::LO;
-    W[SD] = (s1_ - s0_) + TileWin<O, DIM>::R;
-    size = W[0] * W[1] * W[2];
-  }
-  __host__ __device__ static int max_size(const KBins& kb, int waves) {
-    int s = 1;
-    for (int d = 0; d < DIM; ++d) {
-      int ext = kb.T[d];
-      if (d == SD) ext = (ext + waves - 1) / waves;
-      s *= ext + TileWin<O, DIM>::R;
-    }
-    return s;
-  }
-  __device__ __forceinline__ int index(int c, int mx, int my, int mz) const {
-    return c * size + ((mz - o[2]) * W[1] + (my - o[1])) * W[0] + (mx - o[0]);
-  }
-};
-
 // Per-wave mover buffer in LDS: movers are appended with a ballot and a lane prefix
 // count and copied to the global list, with one global atomic per flush, when it fills
 // and at the end of the tile (usually once per tile: the list counter is contended).

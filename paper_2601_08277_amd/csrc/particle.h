@@ -73,11 +73,6 @@ __device__ __forceinline__ int stencil_base(const PartPrep<O, DIM>& p, int c, in
   return p.cell[d] + (st ? win_lo(O, true) + p.ss[d] : win_lo(O, false) + p.sn[d]);
 }
 
-template <int O, int DIM>
-__device__ __forceinline__ const float* stencil_w(const PartPrep<O, DIM>& p, int c, int d) {
-  return (c == d && d < DIM) ? p.ws[d] : p.wn[d];
-}
-
 // Scatter the particle's 3 * (O+1)^DIM contributions through add(c, mx, my, mz, value).
 // The component is a template parameter so every weight index is a compile-time constant.
 template <int C, int O, int DIM, class Add>
