@@ -81,6 +81,56 @@ __device__ __forceinline__ void gather_write(const GatherOut& o, int s, const fl
   for (int c = 0; c < 6; ++c) o.p[c][s] = v[c];
 }
 
+// The valid particles of a tile, enumerated densely: pre[i] = particles in the tile's bins
+// 0..i-1 (i = 0..nb, pre in LDS, `tmp` 256 ints of LDS), so that thread work can run over
+// particles rather than slots (a third of the slots are gaps at the usual slack). Bins
+// hold their particles in a dense prefix of their slots. Returns the count; ends with a
+// barrier.
+__device__ __forceinline__ int tile_valid_prefix(const KBins& B, const TileBox& tb, int* pre,
+                                                 int* tmp) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int per = (tb.nb + nt - 1) / nt;
+  const int lo = min(t * per, tb.nb), hi = min(lo + per, tb.nb);
+  int sum = 0;
+  for (int i = lo; i < hi; ++i) sum += B.len[tb.b0 + i];
+  tmp[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < nt; off <<= 1) {     // inclusive scan of the per-thread sums
+    const int v = t >= off ? tmp[t - off] : 0;
+    __syncthreads();
+    tmp[t] += v;
+    __syncthreads();
+  }
+  int run = t > 0 ? tmp[t - 1] : 0;
+  for (int i = lo; i < hi; ++i) {
+    pre[i] = run;
+    run += B.len[tb.b0 + i];
+  }
+  if (t == nt - 1) pre[tb.nb] = tmp[nt - 1];
+  __syncthreads();
+  return pre[tb.nb];
+}
+
+// Slot of the j-th valid particle of the tile (0 <= j < pre[nb]).
+__device__ __forceinline__ int tile_valid_slot(const KBins& B, const TileBox& tb, const int* pre,
+                                               int j) {
+  int lo = 0, hi = tb.nb;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= j) lo = mid;
+    else hi = mid;
+  }
+  return B.off[tb.b0 + lo] + (j - pre[lo]);
+}
+
+// LDS of the gather and push tile kernels: six field windows, the tile's particle prefix
+// (one int per bin plus one) and the scan's 256 ints.
+template <int O, int DIM>
+static size_t tile_kernel_smem(const KBins& kb) {
+  const size_t nb = (size_t)kb.T[0] * kb.T[1] * kb.T[2];
+  return 6 * sizeof(float) * (size_t)TileWin<O, DIM>::max_size(kb) + (nb + 1 + 256) * sizeof(int);
+}
+
 // Particle-parallel gather from global memory (no bins).
 template <int O, int DIM>
 __global__ __launch_bounds__(256) void k_gather(KGrid G, KPart P, FieldPtrs F, GatherOut o,
@@ -127,17 +177,24 @@ __global__ __launch_bounds__(256) void k_gather_tile(KGrid G, KBins B, KPart P, 
   auto lf = [&](int c, int mx, int my, int mz, float) -> float {
     return sF[c * tw.size + ((mz - tw.o[2]) * tw.W[1] + (my - tw.o[1])) * tw.W[0] + (mx - tw.o[0])];
   };
+  int* pre = (int*)(sF + 6 * tw.size);
+  const int nval = tile_valid_prefix(B, tb, pre, pre + tb.nb + 1);
+  // gap slots get zeros
   const int S0 = B.off[tb.b0], S1 = B.off[tb.b0 + tb.nb];
-  for (int base = S0; base < S1; base += blockDim.x) {
-    const int s = base + threadIdx.x;
+  const float z[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int s = S0 + threadIdx.x; s < S1; s += blockDim.x)
+    if (P.id[s] == PIC_INVALID_ID) gather_write(o, s, z);
+  for (int base = 0; base < nval; base += blockDim.x) {
+    const int j = base + threadIdx.x;
+    const int s = j < nval ? tile_valid_slot(B, tb, pre, j) : 0;
     int cell[3];
     float f[3];
-    const bool ok = s < S1 && P.id[s] != PIC_INVALID_ID &&
+    const bool ok = j < nval &&
                     prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad);
     const bool local = ok && tw.fits_cell(cell);
     float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (local) gather_particle<O, DIM>(cell, f, lf, v);
-    if (s < S1 && (local || !ok)) gather_write(o, s, v);
+    if (j < nval && (local || !ok)) gather_write(o, s, v);
     const int e = wave_append(ok && !local, &B.ctr[CTR_TOTAL]);
     if (e >= 0) list[e] = s;
   }
@@ -166,7 +223,7 @@ __global__ __launch_bounds__(256) void k_gather_list(KGrid G, KBins B, KPart P, 
 template <int O, int DIM>
 static void launch_gather(const KGrid& G, const KPart& P, pic_bins* b, const FieldPtrs& F,
                           const GatherOut& o, hipStream_t s) {
-  const size_t smem = b ? 6 * sizeof(float) * (size_t)TileWin<O, DIM>::max_size(b->kb) : 0;
+  const size_t smem = b ? tile_kernel_smem<O, DIM>(b->kb) : 0;
   if (b && b->sorted_once && smem <= b->max_lds) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->kb.ctr + CTR_TOTAL, (int64_t)1);
     hipLaunchKernelGGL((k_gather_tile<O, DIM>), dim3(b->kb.ntiles + TAIL_BLOCKS), dim3(256), smem, s, G,
@@ -294,12 +351,14 @@ __global__ __launch_bounds__(256) void k_push_tile(KGrid G, KBins B, KPart P, Fi
   auto lf = [&](int c, int mx, int my, int mz, float) -> float {
     return sF[c * tw.size + ((mz - tw.o[2]) * tw.W[1] + (my - tw.o[1])) * tw.W[0] + (mx - tw.o[0])];
   };
-  const int S0 = B.off[tb.b0], S1 = B.off[tb.b0 + tb.nb];
-  for (int base = S0; base < S1; base += blockDim.x) {
-    const int s = base + threadIdx.x;
+  int* pre = (int*)(sF + 6 * tw.size);
+  const int nval = tile_valid_prefix(B, tb, pre, pre + tb.nb + 1);
+  for (int base = 0; base < nval; base += blockDim.x) {
+    const int j = base + threadIdx.x;
+    const int s = j < nval ? tile_valid_slot(B, tb, pre, j) : 0;
     int cell[3];
     float f[3];
-    const bool ok = s < S1 && P.id[s] != PIC_INVALID_ID &&
+    const bool ok = j < nval &&
                     prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad);
     const bool local = ok && tw.fits_cell(cell);
     if (local) {
@@ -335,7 +394,7 @@ __global__ __launch_bounds__(256) void k_push_list(KGrid G, KBins B, KPart P, Fi
 template <int O, int DIM>
 static void launch_push(const KGrid& G, const KPart& P, pic_bins* b, const FieldPtrs& F,
                         double h, double dt, hipStream_t s) {
-  const size_t smem = b ? 6 * sizeof(float) * (size_t)TileWin<O, DIM>::max_size(b->kb) : 0;
+  const size_t smem = b ? tile_kernel_smem<O, DIM>(b->kb) : 0;
   if (b && b->sorted_once && smem <= b->max_lds) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->kb.ctr + CTR_TOTAL, (int64_t)1);
     hipLaunchKernelGGL((k_push_tile<O, DIM>), dim3(b->kb.ntiles), dim3(256), smem, s, G,
