@@ -331,7 +331,7 @@ def bench_c5(args, torch, pic, synth):
                    "cells": ncell, "tile": list(tile)})
     out["roofline"] = {"bound": "hbm", "achieved": byts / (bwd * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": byts / (bwd * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                       "traffic": None, "kernel": "k_backward<3,3>", "bytes_per_launch": byts,
+                       "traffic": None, "kernel": "k_backward_tile<3,3> + k_backward_list<3,3>", "bytes_per_launch": byts,
                        "kernel_ms": bwd}
     out["forward_ms"] = fwd
     out["forward_plus_backward_ms"] = fwd + bwd

@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "deposit_common.h"
+#include "tile_particles.h"
 
 uint32_t* nobins_err_ptr();
 
@@ -184,17 +185,23 @@ __global__ __launch_bounds__(256) void k_backward_tile(KGrid G, KBins B, KPart P
   auto lf = [&](int c, int mx, int my, int mz, float) -> float {
     return sG[tw.index(c, mx, my, mz)];
   };
+  int* pre = (int*)(sG + 3 * tw.size);
+  const int nval = tile_valid_prefix(B, tb, pre, pre + tb.nb + 1);
+  // gap slots get zeros
   const int S0 = B.off[tb.b0], S1 = B.off[tb.b0 + tb.nb];
+  for (int s = S0 + threadIdx.x; s < S1; s += blockDim.x)
+    if (P.id[s] == PIC_INVALID_ID) bwd_zero(s, DIM, dx, dy, dz, dux, duy, duz, dw);
   // uniform trip count: every lane reaches the wave-level list append
-  for (int base = S0; base < S1; base += blockDim.x) {
-    const int s = base + threadIdx.x;
+  for (int base = 0; base < nval; base += blockDim.x) {
+    const int j = base + threadIdx.x;
+    const int s = j < nval ? tile_valid_slot(B, tb, pre, j) : 0;
     int cell[3];
     float f[3];
-    const bool ok = s < S1 && P.id[s] != PIC_INVALID_ID &&
+    const bool ok = j < nval &&
                     prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad);
     const bool local = ok && tw.fits_cell(cell);
     if (local) bwd_particle<O, DIM>(G, P, s, cell, f, lf, dx, dy, dz, dux, duy, duz, dw);
-    else if (s < S1 && !ok) bwd_zero(s, DIM, dx, dy, dz, dux, duy, duz, dw);
+    else if (j < nval && !ok) bwd_zero(s, DIM, dx, dy, dz, dux, duy, duz, dw);
     const int e = wave_append(ok && !local, &B.ctr[CTR_TOTAL]);
     if (e >= 0) list[e] = s;
   }
@@ -240,7 +247,9 @@ template <int O, int DIM>
 static bool launch_bwd_tile(const KGrid& G, const KPart& P, const pic_bins* b, const float* G0,
                             const float* G1, const float* G2, float* dx, float* dy, float* dz,
                             float* dux, float* duy, float* duz, float* dw, hipStream_t s) {
-  const size_t smem = 3 * sizeof(float) * (size_t)TileWin<O, DIM>::max_size(b->kb);
+  const size_t nb = (size_t)b->kb.T[0] * b->kb.T[1] * b->kb.T[2];
+  const size_t smem = 3 * sizeof(float) * (size_t)TileWin<O, DIM>::max_size(b->kb) +
+                      (nb + 1 + 256) * sizeof(int);   // G windows, particle prefix, scan
   if (smem > b->max_lds) return false;
   // the list count lives in the full sort's scratch counter, the list in its bin array
   hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->kb.ctr + CTR_TOTAL, (int64_t)1);
