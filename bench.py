@@ -78,8 +78,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design "
-              f"is described in DESIGN.md and not measured.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs "
+              f"is designed but not built or measured.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2601_08277_amd import pic, synth
@@ -378,7 +378,7 @@ def path_table(pic, torch, grid, parts, bins, N, ncell):
             res[name] = {"particles_per_s": N / (kms * 1e-3), "kernel_ms": kms,
                          "hbm_frac": byts / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "rel_l2_vs_oracle_32cubed": err}
-        except Exception as exc:  # a path this build does not provide
+        except Exception as exc:  # a path the library does not provide for this grid
             res[name] = {"error": str(exc)}
     s_bins.close()
     return res

@@ -47,7 +47,7 @@ extern "C" {
 typedef enum {
   PIC_OK = 0,
   PIC_ERR_INVALID_ARG = -1,       /* bad descriptor, size, pointer or mode            */
-  PIC_ERR_UNSUPPORTED = -2,       /* valid request this build does not implement      */
+  PIC_ERR_UNSUPPORTED = -2,       /* valid request the library does not implement     */
   PIC_ERR_OUT_OF_DOMAIN = -3,     /* a particle (or its stencil) left the domain       */
   PIC_ERR_CAPACITY = -4,          /* particle arrays too small for bins with slack     */
   PIC_ERR_INVALID_PARTICLE = -5,  /* non-finite position                              */
