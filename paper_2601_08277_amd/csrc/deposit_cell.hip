@@ -4,17 +4,19 @@
 // A workgroup owns one particle tile and walks it in groups of 64 consecutive cells (one
 // z-plane of an 8 x 8 x T tile). Bins are contiguous, so a group's particles are one
 // contiguous slot range; a unit is up to CV_CAP particles of one group. Four waves:
-//  producer   (wave 3) stages unit u + 1 while the consumers work on unit u. Lanes = slots,
-//             coalesced loads: position -> cell + float32 offset (FP64 only here) and
-//             amplitude q W v_c; the fused drift and mover detection (stage 1 of Alg. 2)
-//             also run here, once per particle, movers going to an LDS buffer. Offsets and
-//             amplitudes go to a double-buffered LDS stage in cell order, gap slots
-//             skipped. A particle whose cell no longer matches its bin goes to a stale list.
+//  producer   (wave 3) stages unit u + 1 while the consumers work on unit u. Lanes = the
+//             unit's particles (each one's cell found by a binary search over the group's
+//             staged ranges, so gap slots take no lane), coalesced loads: position -> cell
+//             + float32 offset (FP64 only here) and amplitude q W v_c. Offsets and
+//             amplitudes go to a double-buffered LDS stage in cell order. A particle whose
+//             cell no longer matches its bin goes to a stale list.
 //  consumers  (wave c = 0, 1, 2: component c) lanes = cells: each lane walks its cell's
 //             staged particles and accumulates (amp_c s_x) (x) s_y (x) s_z of component c
 //             on the cell's padded stencil window in registers (Eq. 4); after the group's
 //             last unit it adds them to the tile window in LDS (Eq. 5) with plain
-//             read-add-write. The consumers write different components, so they never
+//             read-add-write. After each unit the three waves share the fused drift and
+//             mover detection (stage 1 of Alg. 2) of its slots, movers going to LDS
+//             buffers. The consumers write different components, so they never
 //             share a word. LDS float atomics cost about 190 cycles per wave instruction
 //             on gfx950 (integer ones about 5) and are not used.
 //  end        the consumers add the stale particles (one at a time, lanes = stencil nodes)
@@ -54,7 +56,6 @@ __device__ __forceinline__ int wave_max(int v) {
 
 constexpr int CV_GROUP = 64;    // cells per group (lanes)
 constexpr int CV_CAP = 512;     // staged particles per unit (gap slots skipped)
-constexpr int CV_MAPW = 1024;   // slots covered by one slot -> cell map window
 constexpr int CV_CONS = 3;      // consumer waves, one per current component
 constexpr int CV_PROD = 1;      // producer waves
 constexpr int CV_WAVES = CV_CONS + CV_PROD;
@@ -78,16 +79,15 @@ struct StaleRec {
 };
 
 // LDS layout of one workgroup (bytes): bin offsets and lengths | tile window (3 comps)
-// | two stage buffers f[3][CAP], a[3][CAP] | per producer: slot -> cell map | per
-// consumer: mover buffer | stale list and its count.
+// | two stage buffers f[3][CAP], a[3][CAP] | per consumer: mover buffer | stale list and
+// its count.
 template <int O, int DIM>
 struct CellLayout {
-  size_t win_off, stage_off, map_off, mb_off, stale_off, total;
+  size_t win_off, stage_off, mb_off, stale_off, total;
   __host__ __device__ explicit CellLayout(const KBins& kb) {
     win_off = tile_smem_head(kb);
     stage_off = win_off + (((size_t)3 * TileWin<O, DIM>::max_size(kb) * sizeof(float) + 15) & ~(size_t)15);
-    map_off = stage_off + (size_t)2 * 6 * CV_CAP * sizeof(float);
-    mb_off = map_off + (size_t)CV_PROD * CV_MAPW;
+    mb_off = stage_off + (size_t)2 * 6 * CV_CAP * sizeof(float);
     stale_off = mb_off + (size_t)CV_CONS * 3 * MBUF * sizeof(int32_t);
     total = stale_off + (size_t)CV_STALE * sizeof(StaleRec) + 16;
   }
@@ -220,109 +220,104 @@ __device__ __forceinline__ void cv_particle_global(const KGrid& G, PartPrep<O, D
 }
 
 // Producer wave: stage the unit's particles (staged index in [R0, R0 + CV_CAP)) into one
-// stage buffer, lanes = slots (coalesced loads, the next chunk's loads in flight while the
-// current chunk is processed).
+// stage buffer, lanes = particles: the i-th particle of the unit belongs to the cell whose
+// staged range [st, st + n) holds R0 + i (a binary search over the group's 64 cells), so
+// no lane idles on a gap slot. Coalesced loads; three chunks' loads are in flight ahead
+// of the one being processed (memory latency, not the VALU, bounds this wave).
 template <int O, int DIM, bool RHO>
 __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const KPart& P,
                                          const TileBox& tb, const int32_t* s_off,
                                          const int32_t* s_len, const CellGroup& gr, float* sf,
-                                         float* sa, int8_t* map, StaleRec* stale, int* s_nstale,
+                                         float* sa, StaleRec* stale, int* s_nstale,
                                          float* const* J, uint32_t& bad, float hdt) {
   const int lane = threadIdx.x % PIC_WAVE;
   const int pw = threadIdx.x / PIC_WAVE - CV_CONS;   // producer index
-  const int ex = tb.e[0], exy = tb.e[0] * tb.e[1];
-  for (int lo = gr.S0; lo < gr.S1; lo += CV_MAPW) {
-    const int hi = min(gr.S1, lo + CV_MAPW);
-    wave_lds_sync();
-    for (int i = lane; i < hi - lo; i += PIC_WAVE) map[i] = -1;
-    wave_lds_sync();
-    if (lane < gr.gn) {
-      const int c = gr.g0 + lane;
-      const int a = max(s_off[c], lo), b = min(s_off[c] + s_len[c], hi);
-      for (int q = a; q < b; ++q) map[q - lo] = (int8_t)lane;
+  const int ex = tb.e[0];
+  const int nunit = min(CV_CAP, gr.ntot - gr.R0);
+  const int first = pw * PIC_WAVE, step = CV_PROD * PIC_WAVE;
+  auto fetch = [&](int base, CvRaw& r) {
+    r.si = base + lane;
+    const int g = gr.R0 + r.si;
+    // largest cell c with st[c] <= g: st is non-decreasing over the lanes, and cells past
+    // the group hold st = ntot > g, so c is the (non-empty) cell of staged particle g
+    int c = 0;
+#pragma unroll
+    for (int h = PIC_WAVE / 2; h >= 1; h >>= 1)
+      if (__shfl(gr.st, c + h) <= g) c += h;
+    const int stc = __shfl(gr.st, c);
+    r.lc = r.si < nunit ? c : -1;
+    r.s = r.lc >= 0 ? s_off[gr.g0 + c] + (g - stc) : 0;
+    if (r.lc >= 0) {
+      r.x = P.x[r.s];
+      r.y = P.y[r.s];
+      r.z = DIM == 3 ? P.z[r.s] : 0.0;
+      r.ux = P.ux[r.s];
+      r.uy = P.uy[r.s];
+      r.uz = P.uz[r.s];
+      r.w = P.w[r.s];
     }
-    wave_lds_sync();
-    const int first = lo + pw * PIC_WAVE, step = CV_PROD * PIC_WAVE;
-    auto fetch = [&](int base, CvRaw& r) {
-      r.s = base + lane;
-      r.lc = r.s < hi ? (int)map[r.s - lo] : -1;
-      const int lcs = r.lc < 0 ? 0 : r.lc;
-      r.si = __shfl(gr.st, lcs) + (r.s - s_off[gr.g0 + lcs]) - gr.R0;
-      if (r.si < 0 || r.si >= CV_CAP) r.lc = -1;   // staged in another unit
-      if (r.lc >= 0) {
-        r.x = P.x[r.s];
-        r.y = P.y[r.s];
-        r.z = DIM == 3 ? P.z[r.s] : 0.0;
-        r.ux = P.ux[r.s];
-        r.uy = P.uy[r.s];
-        r.uz = P.uz[r.s];
-        r.w = P.w[r.s];
+  };
+  CvRaw nx1, nx2, nx3;
+  if (first < nunit) fetch(first, nx1);
+  if (first + step < nunit) fetch(first + step, nx2);
+  if (first + 2 * step < nunit) fetch(first + 2 * step, nx3);
+  for (int base = first; base < nunit; base += step) {
+    const CvRaw r = nx1;
+    nx1 = nx2;
+    nx2 = nx3;
+    if (base + 3 * step < nunit) fetch(base + 3 * step, nx3);
+    const int lb = gr.g0 + (r.lc < 0 ? 0 : r.lc);
+    PartPrep<O, DIM> p;
+    double pos[3] = {r.x, r.y, r.z};
+    bool ok = false, mine = false;
+    if (r.lc >= 0) {
+      // time-centred deposition at x + hdt v (hdt = +-dt/2)
+      if (hdt != 0.0f) midpoint_shift<DIM>(G, pos, r.ux, r.uy, r.uz, hdt);
+      ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad);
+      if constexpr (RHO) {
+        p.amp[0] = G.q * r.w;       // charge density: q W, no velocity
+        p.amp[1] = p.amp[2] = 0.0f;
+      } else {
+        prep_amp_rsq(G.q, r.ux, r.uy, r.uz, r.w, 1.0f, p.amp);
       }
-    };
-    // three chunks in flight ahead of the one being processed (memory latency, not the
-    // VALU, bounds this wave)
-    CvRaw nx1, nx2, nx3;
-    if (first < hi) fetch(first, nx1);
-    if (first + step < hi) fetch(first + step, nx2);
-    if (first + 2 * step < hi) fetch(first + 2 * step, nx3);
-    for (int base = first; base < hi; base += step) {
-      const CvRaw r = nx1;
-      nx1 = nx2;
-      nx2 = nx3;
-      if (base + 3 * step < hi) fetch(base + 3 * step, nx3);
-      const int lb = gr.g0 + (r.lc < 0 ? 0 : r.lc);
-      PartPrep<O, DIM> p;
-      double pos[3] = {r.x, r.y, r.z};
-      bool ok = false, mine = false;
-      if (r.lc >= 0) {
-        // time-centred deposition at x + hdt v (hdt = +-dt/2)
-        if (hdt != 0.0f) midpoint_shift<DIM>(G, pos, r.ux, r.uy, r.uz, hdt);
-        ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad);
-        if constexpr (RHO) {
-          p.amp[0] = G.q * r.w;       // charge density: q W, no velocity
-          p.amp[1] = p.amp[2] = 0.0f;
-        } else {
-          prep_amp_rsq(G.q, r.ux, r.uy, r.uz, r.w, 1.0f, p.amp);
-        }
-        // the particle's cell relative to the tile -> local bin (no division)
-        const int lx = p.cell[0] - tb.c0[0], ly = p.cell[1] - tb.c0[1];
-        const int lz = DIM == 3 ? p.cell[2] - tb.c0[2] : 0;
-        const bool in = (unsigned)lx < (unsigned)tb.e[0] && (unsigned)ly < (unsigned)tb.e[1] &&
-                        (unsigned)lz < (unsigned)(DIM == 3 ? tb.e[2] : 1);
-        mine = ok && in && lx + ex * (ly + tb.e[1] * lz) == lb;
-      }
-      // stale particle (its cell no longer matches its bin): kept for the end phase, or,
-      // when the tile's list is full, deposited at once through global atomics
-      const bool st = ok && !mine;
-      const unsigned long long m = __ballot(st);
-      if (m) {
-        int e0 = 0;
-        if (lane == 0) e0 = atomicAdd(s_nstale, (int)__popcll(m));
-        e0 = __shfl(e0, 0);
-        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        if (st) {
-          if (e0 + rank < CV_STALE) {
-            StaleRec& q = stale[e0 + rank];
+      // the particle's cell relative to the tile -> local bin (no division)
+      const int lx = p.cell[0] - tb.c0[0], ly = p.cell[1] - tb.c0[1];
+      const int lz = DIM == 3 ? p.cell[2] - tb.c0[2] : 0;
+      const bool in = (unsigned)lx < (unsigned)tb.e[0] && (unsigned)ly < (unsigned)tb.e[1] &&
+                      (unsigned)lz < (unsigned)(DIM == 3 ? tb.e[2] : 1);
+      mine = ok && in && lx + ex * (ly + tb.e[1] * lz) == lb;
+    }
+    // stale particle (its cell no longer matches its bin): kept for the end phase, or,
+    // when the tile's list is full, deposited at once through global atomics
+    const bool st = ok && !mine;
+    const unsigned long long m = __ballot(st);
+    if (m) {
+      int e0 = 0;
+      if (lane == 0) e0 = atomicAdd(s_nstale, (int)__popcll(m));
+      e0 = __shfl(e0, 0);
+      const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      if (st) {
+        if (e0 + rank < CV_STALE) {
+          StaleRec& q = stale[e0 + rank];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-              q.cell[d] = d < DIM ? p.cell[d] : 0;
-              q.f[d] = d < DIM ? p.f[d] : 0.0f;
-              q.amp[d] = p.amp[d];
-            }
-          } else if constexpr (RHO) {
-            cv_rho_particle_global<O, DIM>(G, p, J[0], bad);
-          } else {
-            cv_particle_global<O, DIM>(G, p, J, bad);
+          for (int d = 0; d < 3; ++d) {
+            q.cell[d] = d < DIM ? p.cell[d] : 0;
+            q.f[d] = d < DIM ? p.f[d] : 0.0f;
+            q.amp[d] = p.amp[d];
           }
+        } else if constexpr (RHO) {
+          cv_rho_particle_global<O, DIM>(G, p, J[0], bad);
+        } else {
+          cv_particle_global<O, DIM>(G, p, J, bad);
         }
       }
-      if (r.lc >= 0) {
+    }
+    if (r.lc >= 0) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          sf[d * CV_CAP + cv_sw(r.si)] = mine ? p.f[d] : 0.0f;
-          sa[d * CV_CAP + cv_sw(r.si)] = mine ? p.amp[d] * CV_AMP_SCALE<O, DIM> : 0.0f;
-        }
+      for (int d = 0; d < 3; ++d) {
+        sf[d * CV_CAP + cv_sw(r.si)] = mine ? p.f[d] : 0.0f;
+        sa[d * CV_CAP + cv_sw(r.si)] = mine ? p.amp[d] * CV_AMP_SCALE<O, DIM> : 0.0f;
       }
     }
   }
@@ -592,8 +587,6 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   const int wave = threadIdx.x / PIC_WAVE;
   const int lane = threadIdx.x % PIC_WAVE;
   const bool producer = wave >= CV_CONS;
-  const int pw = producer ? wave - CV_CONS : 0;
-  int8_t* map_p = (int8_t*)(smem_raw + L.map_off) + pw * CV_MAPW;
   int32_t* mbb = (int32_t*)(smem_raw + L.mb_off) + (producer ? 0 : wave) * 3 * MBUF;
   StaleRec* stale = (StaleRec*)(smem_raw + L.stale_off);
   int* s_nstale = (int*)(smem_raw + L.stale_off + CV_STALE * sizeof(StaleRec));
@@ -613,7 +606,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   // accumulators are not live across the producer's code.
   if (producer) {
     if (cur.g0 < tb.nb)
-      cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, map_p, stale,
+      cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, stale,
                        s_nstale, J, bad, hdt);
     __syncthreads();
     int ub = 0;
@@ -621,7 +614,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
       const CellGroup nxt = cv_next_unit(cur, s_off, s_len, tb.nb, lane);
       if (nxt.g0 < tb.nb) {
         float* nf = stage + (ub ^ 1) * 6 * CV_CAP;
-        cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, map_p, stale,
+        cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, stale,
                          s_nstale, J, bad, hdt);
       }
       __syncthreads();
