@@ -496,9 +496,9 @@ __device__ __forceinline__ void cv_flush_group(const TileBox& tb, const TileWin<
 }
 
 // Consumer wave c, after accumulating a unit: the fused drift (x += v dt, FP64) and mover
-// detection (stage 1 of Alg. 2) for every third 64-slot chunk of the unit's slots, lanes =
-// slots. A slot's bin comes from a binary search over the group's 64 bin offsets; it is
-// done here rather than in the producer, whose loads bound the unit pipeline.
+// detection (stage 1 of Alg. 2) for every third chunk of 64 of the unit's particles, lanes
+// = particles (each one's cell and slot found as in the producer, so gap slots take no
+// lane). It is done here rather than in the producer, whose loads bound the unit pipeline.
 template <int DIM>
 __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, const KPart& P,
                                               const TileBox& tb, const int32_t* s_off,
@@ -509,20 +509,17 @@ __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, co
   const bool emit = flags & PIC_F_EMIT_MOVERS;
   const bool drift = flags & PIC_F_DRIFT;
   const int ex = tb.e[0];
-  for (int base = gr.S0 + wave * PIC_WAVE; base < gr.S1; base += CV_CONS * PIC_WAVE) {
-    const int s = base + lane;
-    int lo = 0, hi = gr.gn;
-    if (s < gr.S1) {
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_off[gr.g0 + mid] <= s) lo = mid;
-        else hi = mid;
-      }
-    }
-    const int k = s - s_off[gr.g0 + lo];
-    const int si = __shfl(gr.st, lo) + k - gr.R0;
-    const bool in_unit = s < gr.S1 && k < s_len[gr.g0 + lo] && si >= 0 && si < CV_CAP;
-    const int lb = gr.g0 + lo;
+  const int nunit = min(CV_CAP, gr.ntot - gr.R0);
+  for (int base = wave * PIC_WAVE; base < nunit; base += CV_CONS * PIC_WAVE) {
+    const int g = gr.R0 + base + lane;
+    int c = 0;
+#pragma unroll
+    for (int h = PIC_WAVE / 2; h >= 1; h >>= 1)
+      if (__shfl(gr.st, c + h) <= g) c += h;
+    const int stc = __shfl(gr.st, c);
+    const bool in_unit = base + lane < nunit;
+    const int s = in_unit ? s_off[gr.g0 + c] + (g - stc) : 0;
+    const int lb = gr.g0 + (in_unit ? c : 0);
     bool ok = false, mv = false;
     int32_t nbn = -1;
     if (in_unit) {
