@@ -56,6 +56,9 @@ __device__ __forceinline__ int wave_max(int v) {
 
 constexpr int CV_GROUP = 64;    // cells per group (lanes)
 constexpr int CV_CAP = 512;     // staged particles per unit (gap slots skipped)
+// Per-unit table (bytes): the cell (group lane) of each staged particle, int8[CV_CAP], then
+// each cell's staged start, int32[CV_GROUP]; double-buffered like the stage.
+constexpr int CV_TAB = CV_CAP + 4 * CV_GROUP;
 constexpr int CV_CONS = 3;      // consumer waves, one per current component
 constexpr int CV_PROD = 1;      // producer waves
 constexpr int CV_WAVES = CV_CONS + CV_PROD;
@@ -79,15 +82,16 @@ struct StaleRec {
 };
 
 // LDS layout of one workgroup (bytes): bin offsets and lengths | tile window (3 comps)
-// | two stage buffers f[3][CAP], a[3][CAP] | per consumer: mover buffer | stale list and
-// its count.
+// | two stage buffers f[3][CAP], a[3][CAP] | two unit tables | per consumer: mover buffer
+// | stale list and its count.
 template <int O, int DIM>
 struct CellLayout {
-  size_t win_off, stage_off, mb_off, stale_off, total;
+  size_t win_off, stage_off, tab_off, mb_off, stale_off, total;
   __host__ __device__ explicit CellLayout(const KBins& kb) {
     win_off = tile_smem_head(kb);
     stage_off = win_off + (((size_t)3 * TileWin<O, DIM>::max_size(kb) * sizeof(float) + 15) & ~(size_t)15);
-    mb_off = stage_off + (size_t)2 * 6 * CV_CAP * sizeof(float);
+    tab_off = stage_off + (size_t)2 * 6 * CV_CAP * sizeof(float);
+    mb_off = tab_off + (size_t)2 * CV_TAB;
     stale_off = mb_off + (size_t)CV_CONS * 3 * MBUF * sizeof(int32_t);
     total = stale_off + (size_t)CV_STALE * sizeof(StaleRec) + 16;
   }
@@ -220,33 +224,34 @@ __device__ __forceinline__ void cv_particle_global(const KGrid& G, PartPrep<O, D
 }
 
 // Producer wave: stage the unit's particles (staged index in [R0, R0 + CV_CAP)) into one
-// stage buffer, lanes = particles: the i-th particle of the unit belongs to the cell whose
-// staged range [st, st + n) holds R0 + i (a binary search over the group's 64 cells), so
-// no lane idles on a gap slot. Coalesced loads; three chunks' loads are in flight ahead
-// of the one being processed (memory latency, not the VALU, bounds this wave).
+// stage buffer, lanes = particles, so no lane idles on a gap slot. The unit's table gives
+// each staged particle's cell (each cell lane writes its own range [st, st + n) of it) and
+// each cell's staged start; the consumers' drift reads the same table. Coalesced loads;
+// three chunks' loads are in flight ahead of the one being processed (memory latency,
+// not the VALU, bounds this wave).
 template <int O, int DIM, bool RHO>
 __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const KPart& P,
                                          const TileBox& tb, const int32_t* s_off,
                                          const int32_t* s_len, const CellGroup& gr, float* sf,
-                                         float* sa, StaleRec* stale, int* s_nstale,
+                                         float* sa, int8_t* tab, StaleRec* stale, int* s_nstale,
                                          float* const* J, uint32_t& bad, float hdt) {
   const int lane = threadIdx.x % PIC_WAVE;
   const int pw = threadIdx.x / PIC_WAVE - CV_CONS;   // producer index
   const int ex = tb.e[0];
   const int nunit = min(CV_CAP, gr.ntot - gr.R0);
   const int first = pw * PIC_WAVE, step = CV_PROD * PIC_WAVE;
+  int32_t* tst = (int32_t*)(tab + CV_CAP);
+  wave_lds_sync();
+  tst[lane] = gr.st;
+  {
+    const int k0 = max(0, gr.R0 - gr.st), k1 = min(gr.n, gr.R0 + nunit - gr.st);
+    for (int k = k0; k < k1; ++k) tab[gr.st + k - gr.R0] = (int8_t)lane;
+  }
+  wave_lds_sync();
   auto fetch = [&](int base, CvRaw& r) {
     r.si = base + lane;
-    const int g = gr.R0 + r.si;
-    // largest cell c with st[c] <= g: st is non-decreasing over the lanes, and cells past
-    // the group hold st = ntot > g, so c is the (non-empty) cell of staged particle g
-    int c = 0;
-#pragma unroll
-    for (int h = PIC_WAVE / 2; h >= 1; h >>= 1)
-      if (__shfl(gr.st, c + h) <= g) c += h;
-    const int stc = __shfl(gr.st, c);
-    r.lc = r.si < nunit ? c : -1;
-    r.s = r.lc >= 0 ? s_off[gr.g0 + c] + (g - stc) : 0;
+    r.lc = r.si < nunit ? (int)tab[r.si] : -1;
+    r.s = r.lc >= 0 ? s_off[gr.g0 + r.lc] + (gr.R0 + r.si - tst[r.lc]) : 0;
     if (r.lc >= 0) {
       r.x = P.x[r.s];
       r.y = P.y[r.s];
@@ -497,28 +502,24 @@ __device__ __forceinline__ void cv_flush_group(const TileBox& tb, const TileWin<
 
 // Consumer wave c, after accumulating a unit: the fused drift (x += v dt, FP64) and mover
 // detection (stage 1 of Alg. 2) for every third chunk of 64 of the unit's particles, lanes
-// = particles (each one's cell and slot found as in the producer, so gap slots take no
-// lane). It is done here rather than in the producer, whose loads bound the unit pipeline.
+// = particles (each one's cell and slot from the unit's table, so gap slots take no lane).
+// It is done here rather than in the producer, whose loads bound the unit pipeline.
 template <int DIM>
 __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, const KPart& P,
                                               const TileBox& tb, const int32_t* s_off,
                                               const int32_t* s_len, const CellGroup& gr,
-                                              int wave, MoverBuf& mb, unsigned flags, double dt,
-                                              uint32_t& bad) {
+                                              const int8_t* tab, int wave, MoverBuf& mb,
+                                              unsigned flags, double dt, uint32_t& bad) {
   const int lane = threadIdx.x % PIC_WAVE;
   const bool emit = flags & PIC_F_EMIT_MOVERS;
   const bool drift = flags & PIC_F_DRIFT;
   const int ex = tb.e[0];
   const int nunit = min(CV_CAP, gr.ntot - gr.R0);
   for (int base = wave * PIC_WAVE; base < nunit; base += CV_CONS * PIC_WAVE) {
-    const int g = gr.R0 + base + lane;
-    int c = 0;
-#pragma unroll
-    for (int h = PIC_WAVE / 2; h >= 1; h >>= 1)
-      if (__shfl(gr.st, c + h) <= g) c += h;
-    const int stc = __shfl(gr.st, c);
-    const bool in_unit = base + lane < nunit;
-    const int s = in_unit ? s_off[gr.g0 + c] + (g - stc) : 0;
+    const int j = base + lane;
+    const bool in_unit = j < nunit;
+    const int c = in_unit ? (int)tab[j] : 0;
+    const int s = in_unit ? s_off[gr.g0 + c] + (gr.R0 + j - ((const int32_t*)(tab + CV_CAP))[c]) : 0;
     const int lb = gr.g0 + (in_unit ? c : 0);
     bool ok = false, mv = false;
     int32_t nbn = -1;
@@ -581,6 +582,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   int32_t* s_len = s_off + tb.nb + 1;
   float* win = (float*)(smem_raw + L.win_off);
   float* stage = (float*)(smem_raw + L.stage_off);
+  int8_t* tab = (int8_t*)(smem_raw + L.tab_off);
   const int wave = threadIdx.x / PIC_WAVE;
   const int lane = threadIdx.x % PIC_WAVE;
   const bool producer = wave >= CV_CONS;
@@ -603,16 +605,16 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   // accumulators are not live across the producer's code.
   if (producer) {
     if (cur.g0 < tb.nb)
-      cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, stale,
-                       s_nstale, J, bad, hdt);
+      cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, tab,
+                            stale, s_nstale, J, bad, hdt);
     __syncthreads();
     int ub = 0;
     while (cur.g0 < tb.nb) {
       const CellGroup nxt = cv_next_unit(cur, s_off, s_len, tb.nb, lane);
       if (nxt.g0 < tb.nb) {
         float* nf = stage + (ub ^ 1) * 6 * CV_CAP;
-        cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP, stale,
-                         s_nstale, J, bad, hdt);
+        cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP,
+                              tab + (ub ^ 1) * CV_TAB, stale, s_nstale, J, bad, hdt);
       }
       __syncthreads();
       cur = nxt;
@@ -634,7 +636,8 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
       else if (wave == 1) cv_consume<O, DIM, 1, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       else cv_consume<O, DIM, 2, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       if (!RHO && (flags & (PIC_F_DRIFT | PIC_F_EMIT_MOVERS)))
-        cv_drift_unit<DIM>(G, B, P, tb, s_off, s_len, cur, wave, mb, flags, dt, bad);
+        cv_drift_unit<DIM>(G, B, P, tb, s_off, s_len, cur, tab + ub * CV_TAB, wave, mb, flags,
+                           dt, bad);
       __syncthreads();
       cur = nxt;
       ub ^= 1;
