@@ -56,9 +56,11 @@ __device__ __forceinline__ int wave_max(int v) {
 
 constexpr int CV_GROUP = 64;    // cells per group (lanes)
 constexpr int CV_CAP = 512;     // staged particles per unit (gap slots skipped)
-// Per-unit table (bytes): the cell (group lane) of each staged particle, int8[CV_CAP], then
-// each cell's staged start, int32[CV_GROUP]; double-buffered like the stage.
+// Per-unit table (bytes): the cell (group lane) of each staged particle, int8[CV_CAP], with
+// CV_TAB_BAD set when the producer found its position outside the domain or not finite,
+// then each cell's staged start, int32[CV_GROUP]; double-buffered like the stage.
 constexpr int CV_TAB = CV_CAP + 4 * CV_GROUP;
+constexpr int CV_TAB_BAD = 64;   // table flag: the particle's staged position is not valid
 constexpr int CV_CONS = 3;      // consumer waves, one per current component
 constexpr int CV_PROD = 1;      // producer waves
 constexpr int CV_WAVES = CV_CONS + CV_PROD;
@@ -279,6 +281,7 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
       // time-centred deposition at x + hdt v (hdt = +-dt/2)
       if (hdt != 0.0f) midpoint_shift<DIM>(G, pos, r.ux, r.uy, r.uz, hdt);
       ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], p.cell, p.f, bad);
+      if (!ok) tab[r.si] = (int8_t)(r.lc | CV_TAB_BAD);   // the drift skips it
       if constexpr (RHO) {
         p.amp[0] = G.q * r.w;       // charge density: q W, no velocity
         p.amp[1] = p.amp[2] = 0.0f;
@@ -508,8 +511,9 @@ template <int DIM>
 __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, const KPart& P,
                                               const TileBox& tb, const int32_t* s_off,
                                               const int32_t* s_len, const CellGroup& gr,
-                                              const int8_t* tab, int wave, MoverBuf& mb,
-                                              unsigned flags, double dt, uint32_t& bad) {
+                                              const int8_t* tab, bool tab_ok, int wave,
+                                              MoverBuf& mb, unsigned flags, double dt,
+                                              uint32_t& bad) {
   const int lane = threadIdx.x % PIC_WAVE;
   const bool emit = flags & PIC_F_EMIT_MOVERS;
   const bool drift = flags & PIC_F_DRIFT;
@@ -518,7 +522,8 @@ __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, co
   for (int base = wave * PIC_WAVE; base < nunit; base += CV_CONS * PIC_WAVE) {
     const int j = base + lane;
     const bool in_unit = j < nunit;
-    const int c = in_unit ? (int)tab[j] : 0;
+    const int tv = in_unit ? (int)tab[j] : 0;
+    const int c = tv & (CV_GROUP - 1);
     const int s = in_unit ? s_off[gr.g0 + c] + (gr.R0 + j - ((const int32_t*)(tab + CV_CAP))[c]) : 0;
     const int lb = gr.g0 + (in_unit ? c : 0);
     bool ok = false, mv = false;
@@ -528,7 +533,9 @@ __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, co
       int c1[3];
       float f1[3];
       uint32_t nb0 = 0;   // errors are reported by the producer
-      ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], c1, f1, nb0);
+      // the producer checked this same position unless it staged a shifted one
+      if (tab_ok) ok = !(tv & CV_TAB_BAD);
+      else ok = prep_cell<DIM>(G, pos[0], pos[1], pos[2], c1, f1, nb0);
       if (ok && drift) {
         drift_one<DIM>(G, pos, P.ux[s], P.uy[s], P.uz[s], dt);
         P.x[s] = pos[0];
@@ -636,8 +643,8 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
       else if (wave == 1) cv_consume<O, DIM, 1, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       else cv_consume<O, DIM, 2, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       if (!RHO && (flags & (PIC_F_DRIFT | PIC_F_EMIT_MOVERS)))
-        cv_drift_unit<DIM>(G, B, P, tb, s_off, s_len, cur, tab + ub * CV_TAB, wave, mb, flags,
-                           dt, bad);
+        cv_drift_unit<DIM>(G, B, P, tb, s_off, s_len, cur, tab + ub * CV_TAB, hdt == 0.0f, wave,
+                           mb, flags, dt, bad);
       __syncthreads();
       cur = nxt;
       ub ^= 1;
