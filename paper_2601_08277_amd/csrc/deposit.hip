@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void k_halo_tile(KGrid G, KBins B, float* __re
                                                    float* __restrict__ J1,
                                                    float* __restrict__ J2) {
   extern __shared__ __align__(16) int32_t sh[];
-  halo_tile_body<O, DIM, RHO>(G, B, J0, J1, J2, blockIdx.x, sh);
+  halo_tile_body<O, DIM, RHO>(G, B, J0, J1, J2, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
 // Batched window sum: one workgroup per (patch, tile) work item of the plan.

@@ -668,7 +668,7 @@ __global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 3) void k_dep_cell_valu(
     KGrid G, KBins B, KPart P, float* __restrict__ J0, float* __restrict__ J1,
     float* __restrict__ J2, unsigned flags, double dt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cell_tile<O, DIM>(G, B, P, J0, J1, J2, flags, dt, blockIdx.x, smem_raw);
+  cell_tile<O, DIM>(G, B, P, J0, J1, J2, flags, dt, xcd_tile(blockIdx.x, gridDim.x), smem_raw);
 }
 
 // Charge density on the same tiles: the three component waves take every third particle of
@@ -678,7 +678,8 @@ __global__ __launch_bounds__(CV_WAVES * PIC_WAVE, 3) void k_dep_cell_rho(KGrid G
                                                                          KPart P,
                                                                          float* __restrict__ rho) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  cell_tile<O, DIM, true>(G, B, P, rho, rho, rho, 0u, 0.0, blockIdx.x, smem_raw);
+  cell_tile<O, DIM, true>(G, B, P, rho, rho, rho, 0u, 0.0, xcd_tile(blockIdx.x, gridDim.x),
+                          smem_raw);
 }
 
 // Persistent batched deposition (3D patches, any order): each workgroup pulls (patch,

@@ -226,6 +226,16 @@ struct TileBox {
   int32_t nb;  // bins (cells) in the tile
 };
 
+// Tile of workgroup b in a one-workgroup-per-tile launch of n workgroups. Workgroups go to
+// the 8 XCDs in turn (b mod 8), so XCD j is given the j-th contiguous eighth of the tiles:
+// neighbouring tiles, which read each other's window halos, then share one L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int X = 8;
+  const int q = n / X, r = n % X;
+  const int j = b % X, k = b / X;
+  return j * q + min(j, r) + k;
+}
+
 __host__ __device__ __forceinline__ TileBox tile_box(const int n[3], const int T[3],
                                                      const int nt[3], int t) {
   TileBox tb;
