@@ -96,15 +96,33 @@ void scan_exclusive_i32(pic_bins* b, int32_t* data, int64_t n, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------------
+// One particle's payload. Copies load all eight fields before storing any: the arrays may
+// alias (source and destination are often the same particle arrays), so a store placed
+// between two loads would keep the second load waiting for the first store.
+struct Payload {
+  double x, y, z;
+  float ux, uy, uz, w;
+  int32_t id;
+};
+
+__device__ __forceinline__ Payload load_slot(const KPart& S, int s) {
+  return Payload{S.x[s], S.y[s], S.z[s], S.ux[s], S.uy[s], S.uz[s], S.w[s], S.id[s]};
+}
+
+__device__ __forceinline__ void store_slot(const KPart& D, int d, const Payload& p) {
+  D.x[d] = p.x;
+  D.y[d] = p.y;
+  D.z[d] = p.z;
+  D.ux[d] = p.ux;
+  D.uy[d] = p.uy;
+  D.uz[d] = p.uz;
+  D.w[d] = p.w;
+  D.id[d] = p.id;
+}
+
 __device__ __forceinline__ void copy_slot(const KPart& D, int d, const KPart& S, int s) {
-  D.x[d] = S.x[s];
-  D.y[d] = S.y[s];
-  D.z[d] = S.z[s];
-  D.ux[d] = S.ux[s];
-  D.uy[d] = S.uy[s];
-  D.uz[d] = S.uz[s];
-  D.w[d] = S.w[s];
-  D.id[d] = S.id[s];
+  const Payload p = load_slot(S, s);
+  store_slot(D, d, p);
 }
 
 __device__ __forceinline__ void set_gap(const KPart& D, int d) {
@@ -119,17 +137,9 @@ __device__ __forceinline__ void set_gap(const KPart& D, int d) {
 }
 
 __device__ __forceinline__ void swap_slots(const KPart& D, int a, int c) {
-  double t;
-  float u;
-  int32_t k;
-  t = D.x[a]; D.x[a] = D.x[c]; D.x[c] = t;
-  t = D.y[a]; D.y[a] = D.y[c]; D.y[c] = t;
-  t = D.z[a]; D.z[a] = D.z[c]; D.z[c] = t;
-  u = D.ux[a]; D.ux[a] = D.ux[c]; D.ux[c] = u;
-  u = D.uy[a]; D.uy[a] = D.uy[c]; D.uy[c] = u;
-  u = D.uz[a]; D.uz[a] = D.uz[c]; D.uz[c] = u;
-  u = D.w[a]; D.w[a] = D.w[c]; D.w[c] = u;
-  k = D.id[a]; D.id[a] = D.id[c]; D.id[c] = k;
+  const Payload pa = load_slot(D, a), pc = load_slot(D, c);
+  store_slot(D, a, pc);
+  store_slot(D, c, pa);
 }
 
 // Sort slots [o, o + n) by id (insertion sort on the payload; bins are small).
@@ -392,12 +402,13 @@ __global__ __launch_bounds__(256) void k_insert(KBins B, KPart P, const int32_t*
   const int nmov = min(B.ctr[CTR_NMOV], B.max_movers);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nmov; e += gridDim.x * blockDim.x) {
     const int s = B.mv_slot[e], ob = B.mv_old[e], nb = B.mv_new[e];
+    const Payload pl = load_slot(P, s);   // in flight while the destination is claimed
     const int k = atomicAdd(&B.ins_cnt[nb], 1);
     const int pos = B.len[nb] + k;
     const int cap = B.off[nb + 1] - B.off[nb];
     const bool fits = pos < cap;
     if (fits) {
-      copy_slot(P, B.off[nb] + pos, P, s);
+      store_slot(P, B.off[nb] + pos, pl);
       P.id[s] = PIC_INVALID_ID;
       P.w[s] = 0.0f;
       atomicAdd(&B.moved_out[ob], 1);
