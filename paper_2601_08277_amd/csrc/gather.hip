@@ -242,6 +242,9 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
 template <int DIM>
 __device__ __forceinline__ void boris_move(const KGrid& G, const KPart& P, int s, const float* v,
                                            double h, double dt) {
+  // every load before the first store: the arrays may alias, which would keep a later
+  // load behind an earlier store
+  double pos[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
   double um[3] = {(double)P.ux[s] + h * (double)v[0], (double)P.uy[s] + h * (double)v[1],
                   (double)P.uz[s] + h * (double)v[2]};
   const double gm = __builtin_sqrt(1.0 + ((um[0] * um[0] + um[1] * um[1]) + um[2] * um[2]));
@@ -259,7 +262,6 @@ __device__ __forceinline__ void boris_move(const KGrid& G, const KPart& P, int s
   P.ux[s] = un[0];
   P.uy[s] = un[1];
   P.uz[s] = un[2];
-  double pos[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
   drift_one<DIM>(G, pos, un[0], un[1], un[2], dt);
   P.x[s] = pos[0];
   P.y[s] = pos[1];
