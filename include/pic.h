@@ -251,7 +251,7 @@ pic_status pic_push(const pic_grid* grid, pic_particles* p, pic_bins* bins, cons
                     const float* Bz, double qm, double dt, unsigned flags, hipStream_t stream);
 
 /* Charge-conserving current (Esirkepov's density decomposition, the scheme the paper lists
- * as unsupported in Sec. 6): for each valid particle moving from (x_old, y_old, z_old) to
+ * as unsupported in Sec. 7): for each valid particle moving from (x_old, y_old, z_old) to
  * its current position in p during grid->dt, J_d on the faces i+1/2 is
  * -q W dx_d/dt times the running sum along d of W_d, with W_d built from the 1D nodal
  * weights at the two positions (order grid->order, o+2 nodes per dimension), so that

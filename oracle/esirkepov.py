@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 
 The paper deposits the direct current of Eq. 1 and names charge-conserving schemes
-(Esirkepov / Vay) as not supported (Sec. 6, limitations). This oracle follows the
+(Esirkepov / Vay) as not supported (Sec. 7, limitations). This oracle follows the
 published method: T. Zh. Esirkepov, "Exact charge conservation scheme for
 Particle-in-Cell simulation with an arbitrary form-factor", Comput. Phys. Commun. 135
 (2001) 144. For a particle that moves from grid coordinate xi0 to xi1 in one step

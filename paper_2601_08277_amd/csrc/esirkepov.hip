@@ -1,7 +1,7 @@
 // Charge-conserving current deposition (Esirkepov's density decomposition).
 //
 // The paper deposits the direct current of Eq. 1 and lists charge-conserving schemes as
-// unsupported (Sec. 6). For a particle moving from grid coordinate xi0 to xi1 within one
+// unsupported (Sec. 7). For a particle moving from grid coordinate xi0 to xi1 within one
 // step (less than a cell per dimension), with 1D nodal B-spline weights S0, S1 on a common
 // box of O+2 nodes per dimension, DS = S1 - S0 and M = (S0 + S1)/2, the published
 // decomposition (Esirkepov, Comput. Phys. Commun. 135 (2001) 144) gives in 3D
