@@ -14,20 +14,37 @@
 
 uint32_t* nobins_err_ptr();
 
-// sum over the stencil of F at the particle, with per-dimension staggering SX, SY, SZ.
-template <int O, int DIM, bool SX, bool SY, bool SZ, class Fetch>
-__device__ __forceinline__ float gather_one(const int* cell, const float* f, int c,
-                                            Fetch&& fetch) {
-  float wx[O + 1], wy[O + 1], wz[O + 1];
-  const int bx = cell[0] + win_lo(O, SX) + shape_w<O, SX>(f[0], wx);
-  const int by = cell[1] + win_lo(O, SY) + shape_w<O, SY>(f[1], wy);
-  int bz = 0;
-  if constexpr (DIM == 3) {
-    bz = cell[2] + win_lo(O, SZ) + shape_w<O, SZ>(f[2], wz);
-  } else {
+// The 1D weights and first nodes of one dimension, nodal and half-cell staggered: the six
+// field components use only these six vectors, so they are formed once per particle.
+template <int O>
+struct GatherW {
+  float w[2][O + 1];   // [staggered][k]
+  int b[2];
+};
+
+template <int O, int DIM>
+__device__ __forceinline__ void gather_weights(const int* cell, const float* f, GatherW<O>* gw) {
 #pragma unroll
-    for (int k = 0; k <= O; ++k) wz[k] = k == 0 ? 1.0f : 0.0f;
+  for (int d = 0; d < 3; ++d) {
+    if (d < DIM) {
+      gw[d].b[0] = cell[d] + win_lo(O, false) + shape_w<O, false>(f[d], gw[d].w[0]);
+      gw[d].b[1] = cell[d] + win_lo(O, true) + shape_w<O, true>(f[d], gw[d].w[1]);
+    } else {          // 2D: one node along z with weight 1
+#pragma unroll
+      for (int k = 0; k <= O; ++k) gw[d].w[0][k] = gw[d].w[1][k] = k == 0 ? 1.0f : 0.0f;
+      gw[d].b[0] = gw[d].b[1] = 0;
+    }
   }
+}
+
+// Sum over the stencil of field component c at the particle, with per-dimension
+// staggering SX, SY, SZ.
+template <int O, int DIM, bool SX, bool SY, bool SZ, class Fetch>
+__device__ __forceinline__ float gather_one(const GatherW<O>* gw, int c, Fetch&& fetch) {
+  const float* wx = gw[0].w[SX];
+  const float* wy = gw[1].w[SY];
+  const float* wz = gw[2].w[SZ];
+  const int bx = gw[0].b[SX], by = gw[1].b[SY], bz = gw[2].b[SZ];
   float acc = 0.0f;
 #pragma unroll
   for (int kz = 0; kz < (DIM == 3 ? O + 1 : 1); ++kz) {
@@ -48,12 +65,14 @@ template <int O, int DIM, class Fetch>
 __device__ __forceinline__ void gather_particle(const int* cell, const float* f, Fetch&& fetch,
                                                 float* out) {
   constexpr bool Z3 = DIM == 3;
-  out[0] = gather_one<O, DIM, true, false, false>(cell, f, 0, fetch);
-  out[1] = gather_one<O, DIM, false, true, false>(cell, f, 1, fetch);
-  out[2] = gather_one<O, DIM, false, false, Z3>(cell, f, 2, fetch);
-  out[3] = gather_one<O, DIM, false, true, Z3>(cell, f, 3, fetch);
-  out[4] = gather_one<O, DIM, true, false, Z3>(cell, f, 4, fetch);
-  out[5] = gather_one<O, DIM, true, true, false>(cell, f, 5, fetch);
+  GatherW<O> gw[3];
+  gather_weights<O, DIM>(cell, f, gw);
+  out[0] = gather_one<O, DIM, true, false, false>(gw, 0, fetch);
+  out[1] = gather_one<O, DIM, false, true, false>(gw, 1, fetch);
+  out[2] = gather_one<O, DIM, false, false, Z3>(gw, 2, fetch);
+  out[3] = gather_one<O, DIM, false, true, Z3>(gw, 3, fetch);
+  out[4] = gather_one<O, DIM, true, false, Z3>(gw, 4, fetch);
+  out[5] = gather_one<O, DIM, true, true, false>(gw, 5, fetch);
 }
 
 struct GatherOut {
