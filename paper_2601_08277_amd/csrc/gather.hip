@@ -96,6 +96,56 @@ struct FieldPtrs {
   const float* f[6];
 };
 
+// Weight k of a stencil vector by select, for a lane-dependent k (an indexed register
+// array would go to scratch memory).
+template <int O>
+__device__ __forceinline__ float gw_pick(const float* w, int k) {
+  float v = w[0];
+#pragma unroll
+  for (int i = 1; i <= O; ++i) v = k == i ? w[i] : v;
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int m = PIC_WAVE / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+
+template <int O, int DIM, bool SX, bool SY, bool SZ>
+__device__ __forceinline__ float wave_gather_one(const GatherW<O>* gw, int c, int kx, int ky,
+                                                 int kz, bool act, const FieldFetch& ff) {
+  float t = 0.0f;
+  if (act) {
+    const float w = gw_pick<O>(gw[0].w[SX], kx) * gw_pick<O>(gw[1].w[SY], ky) *
+                    gw_pick<O>(gw[2].w[SZ], kz);
+    t = w * ff(c, gw[0].b[SX] + kx, gw[1].b[SY] + ky, gw[2].b[SZ] + kz, w);
+  }
+  return wave_sum(t);
+}
+
+// The six components of one particle gathered by a whole wave, lanes = stencil nodes (for
+// the few particles outside their tile's window: their nodes are read from global memory
+// by 64 lanes at once instead of one after another). Every lane returns the sums.
+template <int O, int DIM>
+__device__ __forceinline__ void wave_gather(const int* cell, const float* f, const FieldFetch& ff,
+                                            float* v) {
+  constexpr int NS = (O + 1) * (O + 1) * (DIM == 3 ? O + 1 : 1);
+  constexpr bool Z3 = DIM == 3;
+  GatherW<O> gw[3];
+  gather_weights<O, DIM>(cell, f, gw);
+  const int lane = threadIdx.x % PIC_WAVE;
+  const bool act = lane < NS;
+  const int kx = lane % (O + 1), ky = (lane / (O + 1)) % (O + 1);
+  const int kz = DIM == 3 ? lane / ((O + 1) * (O + 1)) : 0;
+  v[0] = wave_gather_one<O, DIM, true, false, false>(gw, 0, kx, ky, kz, act, ff);
+  v[1] = wave_gather_one<O, DIM, false, true, false>(gw, 1, kx, ky, kz, act, ff);
+  v[2] = wave_gather_one<O, DIM, false, false, Z3>(gw, 2, kx, ky, kz, act, ff);
+  v[3] = wave_gather_one<O, DIM, false, true, Z3>(gw, 3, kx, ky, kz, act, ff);
+  v[4] = wave_gather_one<O, DIM, true, false, Z3>(gw, 4, kx, ky, kz, act, ff);
+  v[5] = wave_gather_one<O, DIM, true, true, false>(gw, 5, kx, ky, kz, act, ff);
+}
+
 __device__ __forceinline__ void gather_write(const GatherOut& o, int s, const float* v) {
 #pragma unroll
   for (int c = 0; c < 6; ++c) o.p[c][s] = v[c];
@@ -186,14 +236,17 @@ __global__ __launch_bounds__(256) void k_gather_list(KGrid G, KBins B, KPart P, 
   uint32_t bad = 0;
   const FieldFetch ff{G, F.f, bad};
   const int n = B.ctr[CTR_TOTAL];
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x % PIC_WAVE;
+  const int nw = gridDim.x * (blockDim.x / PIC_WAVE);
+  // one listed particle per wave (wave-uniform loop)
+  for (int e = blockIdx.x * (blockDim.x / PIC_WAVE) + threadIdx.x / PIC_WAVE; e < n; e += nw) {
     const int s = list[e];
     int cell[3];
     float f[3];
     float v[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad))
-      gather_particle<O, DIM>(cell, f, ff, v);
-    gather_write(o, s, v);
+      wave_gather<O, DIM>(cell, f, ff, v);
+    if (lane == 0) gather_write(o, s, v);
   }
   if (bad) atomicOr(B.err, bad);
 }
@@ -359,14 +412,17 @@ __global__ __launch_bounds__(256) void k_push_list(KGrid G, KBins B, KPart P, Fi
   uint32_t bad = 0;
   const FieldFetch ff{G, F.f, bad};
   const int n = B.ctr[CTR_TOTAL];
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x % PIC_WAVE;
+  const int nw = gridDim.x * (blockDim.x / PIC_WAVE);
+  // one listed particle per wave (wave-uniform loop); lane 0 pushes it
+  for (int e = blockIdx.x * (blockDim.x / PIC_WAVE) + threadIdx.x / PIC_WAVE; e < n; e += nw) {
     const int s = list[e];
     int cell[3];
     float f[3];
     if (!prep_cell<DIM>(G, P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0, cell, f, bad)) continue;
     float v[6];
-    gather_particle<O, DIM>(cell, f, ff, v);
-    boris_move<DIM>(G, P, s, v, h, dt);
+    wave_gather<O, DIM>(cell, f, ff, v);
+    if (lane == 0) boris_move<DIM>(G, P, s, v, h, dt);
   }
   if (bad) atomicOr(B.err, bad);
 }
