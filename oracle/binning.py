@@ -22,7 +22,10 @@ The policy (Sec. 4.4) evaluates five triggers in priority order after each step:
 Readings: trigger 4 compares the fraction of empty slots over all bins with both
 thresholds (too full when below empty_ratio, too sparse when above full_ratio); the
 baseline of trigger 5 is the performance of the first step after the last global sort,
-higher meaning better. Defaults are the paper's parameter table (Appendix A).
+higher meaning better. Defaults are the paper's parameter table (Appendix A). The policy
+acts on the statistics known when it decides (Alg. 1 evaluates it on the step's collected
+statistics): while no statistics of a step after the last global sort are known, the
+empty-slot ratio is unknown (None) and trigger 4 cannot fire.
 """
 import numpy as np
 
@@ -83,7 +86,8 @@ def should_global_sort(steps_since_sort, rebuilds_since_sort, empty_slot_ratio,
         return True, 2
     if rebuilds_since_sort > p["rebuild_count"]:
         return True, 3
-    if empty_slot_ratio < p["empty_ratio"] or empty_slot_ratio > p["full_ratio"]:
+    if empty_slot_ratio is not None and (empty_slot_ratio < p["empty_ratio"]
+                                         or empty_slot_ratio > p["full_ratio"]):
         return True, 4
     if (p["perf_enable"] and perf is not None and perf_baseline is not None
             and perf < p["perf_degrad"] * perf_baseline):

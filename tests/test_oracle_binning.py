@@ -85,6 +85,9 @@ def test_drift_is_plain_kinematics():
     ((20, 0, 0.90, None, None), (True, 4)),     # too many empty slots
     ((20, 0, 0.25, 0.7, 1.0), (True, 5)),       # performance below 80 % of baseline
     ((20, 0, 0.25, 0.85, 1.0), (False, 0)),
+    ((20, 0, None, None, None), (False, 0)),    # empty ratio not known yet: no trigger 4
+    ((20, 101, None, None, None), (True, 3)),
+    ((20, 0, None, 0.7, 1.0), (True, 5)),
 ])
 def test_policy_truth_table(case):
     args, want = case
