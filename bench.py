@@ -24,6 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+_T0 = time.perf_counter()
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "deposit_cell_valu_c2_128cubed_o3_hbm_counters.md")
 
 
@@ -65,6 +71,7 @@ def parse():
     ap.add_argument("--tile", default="8x8x4", help="particle tile, cells (x by y by z)")
     ap.add_argument("--slack", type=float, default=0.5, help="free slots per bin, per particle")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 256x256x1024 LWFA leg")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
                     help="c2: 128^3 uniform step (default); c3: 256x256x1024 LWFA snapshot; "
@@ -92,6 +99,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     n3 = (args.n, args.n, args.n)
+    log("generating the uniform-plasma workload")
     params, arrays = synth.c2(n=n3, ppc=args.ppc)
     N = arrays["x"].size
     ncell = int(np.prod(n3))
@@ -99,18 +107,17 @@ def main():
     grid = pic.Grid(params)
     nslots = pic.slots_for(N, ncell, slack)
     parts = pic.Particles.from_arrays(arrays, nslots)
+    del arrays
     tile = tuple(int(t) for t in args.tile.split("x"))
     bins = pic.Bins(grid, tile, slack, nslots)
     pic.rebin(grid, parts, bins, pic.REBIN_FULL)
     J = pic.new_J(grid)
     path = pic.PATH_NAMES[args.path]
-    flags = pic.F_ACCUMULATE | pic.F_DRIFT | pic.F_EMIT_MOVERS
+    flags = pic.F_DRIFT | pic.F_EMIT_MOVERS     # J overwritten by the call itself
     pol = pic.policy()
     stream = torch.cuda.current_stream()
 
     def step(ev=None):
-        for j in J:
-            j.zero_()
         if ev:
             ev[0].record(stream)
         pic.deposit(grid, parts, bins, path, flags, J=J)
@@ -120,8 +127,11 @@ def main():
         if ev:
             ev[2].record(stream)
 
+    log("warm-up steps")
     for _ in range(args.warmup):
         step()
+    torch.cuda.synchronize()
+    seq0 = len(bins.history())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -130,20 +140,22 @@ def main():
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
     value = N / (ms * 1e-3)
-    st = bins.stats()
+    timed = bins.history(first=seq0)[: args.steps]
+    log(f"timed steps: {ms:.3f} ms per step")
 
-    # per-kernel split of the step, HIP events on the launch stream
+    # per-call split of the step, HIP events on the launch stream
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     for e in evs:
         step(e)
     torch.cuda.synchronize()
     dep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     reb_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    st2 = bins.stats()
+    inc = [h for h in timed if h["mode"] == pic.REBIN_INCREMENTAL]
 
-    # algorithmic bytes of the fused deposition kernel (per launch)
-    movers = st2["n_moved"]
-    dep_bytes = N * (24 + 12 + 4) + N * 24 + ncell * 24 + movers * 12
+    # algorithmic bytes of one deposition call: 40 B per particle in, 12 B per cell of J out
+    dep_bytes = N * 40 + ncell * 12
+    movers = float(np.mean([h["n_moved"] for h in inc])) if inc else 0.0
+    ext_bytes = dep_bytes + N * 24 + movers * 12   # + drift write-back and mover list
     achieved = dep_bytes / (dep_ms * 1e-3) / 1e9
     out = {
         "metric": "particles deposited/s, order-3 3D, split-MFMA vs FP32 at stated err; % roofline",
@@ -160,7 +172,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"uniform plasma {args.n}^3 cells, {args.ppc} per cell, order 3, "
                                f"periodic, u~N(0,0.05), dt 0.2; step = deposit (fused drift + "
-                               f"mover detection) + incremental rebin",
+                               f"mover detection) + rebin under the re-sort policy",
                    "particles": int(N), "cells": ncell, "path": args.path, "tile": list(tile),
                    "slack": slack},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -168,14 +180,28 @@ def main():
                      "traffic": measured_traffic(args.path, tile, args.n, args.ppc, slack),
                      "kernel": "pic_deposit call = k_dep_cell_valu<3,3> + k_halo_tile<3,3> "
                                "(fused drift + mover detection)",
-                     "bytes_per_launch": dep_bytes, "kernel_ms": dep_ms},
+                     "bytes_per_launch": dep_bytes,
+                     "bytes_basis": "40 B per particle + 12 B per cell",
+                     "kernel_ms": dep_ms,
+                     "bytes_with_drift_and_movers": ext_bytes},
         "breakdown_ms": {"deposit": dep_ms, "rebin": reb_ms,
                          "other": max(0.0, ms - dep_ms - reb_ms)},
-        "rebin": {"movers_per_step": int(movers), "mover_fraction": movers / N,
-                  "overflow": int(st2["n_overflow"]), "local_rebuilds": int(st2["n_local_rebuilds"]),
-                  "empty_slot_ratio": st2["empty_slot_ratio"], "global_sorts": st2["n_global_sorts"]},
+        "rebin": {"movers_per_step": movers, "mover_fraction": movers / N,
+                  "overflow_per_step": float(np.mean([h["n_overflow"] for h in inc])) if inc else 0.0,
+                  "local_rebuilds_per_step": float(np.mean([h["n_local_rebuilds"] for h in inc]))
+                  if inc else 0.0,
+                  "empty_slot_ratio": timed[-1]["empty_slot_ratio"] if timed else None,
+                  "global_sorts_in_timed_steps": sum(h["mode"] == pic.REBIN_FULL for h in timed),
+                  "sort_triggers_in_timed_steps": [h["trigger"] for h in timed
+                                                   if h["mode"] == pic.REBIN_FULL],
+                  "policy_lag_calls": pic.POLICY_LAG},
     }
     if not args.no_extras:
+        procs = oracle_procs()
+        log(f"full-size check against the oracle ({procs} processes)")
+        out["full_size_check"], full_t = full_size_check(pic, torch, grid, parts, bins, J, path,
+                                                         params, procs)
+        log("per-path table, charge density, gather, ablations, midpoint, Esirkepov, cycle")
         out["paths"] = path_table(pic, torch, grid, parts, bins, N, ncell)
         out["charge_density"] = rho_line(pic, torch, grid, parts, bins, N, ncell)
         out["field_gather"] = gather_line(pic, torch, grid, parts, bins, N, ncell)
@@ -184,11 +210,17 @@ def main():
         out["esirkepov_deposit"] = esirkepov_line(pic, torch, grid, parts, bins, N, ncell)
         # last: the push moves the snapshot's particles
         out["pic_cycle"] = cycle_line(pic, torch, grid, parts, bins, N, ncell)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        log("CPU baseline")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, N, full_t, procs)
         bw = copy_bandwidth(torch)
         out["hbm_copy_GBps"] = bw
         out["roofline"]["frac_vs_measured_copy"] = achieved / bw
     bins.close()
+    del parts, J
+    torch.cuda.empty_cache()
+    if not args.no_extras and not args.no_c3:
+        log("laser-wakefield-shaped 256x256x1024 leg")
+        out["c3"] = c3_leg(args, torch, pic, synth, oracle_procs())
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -197,6 +229,66 @@ def main():
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * src.numel() * 4
     print(json.dumps(out), flush=True)
+
+
+# ---- the FP64 oracle on all host cores (checker and CPU baseline, never timed as `value`)
+def oracle_procs():
+    """Worker processes for the oracle: the host cores this process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def _oracle_chunk(task):
+    """One chunk of particles through the oracle (runs in a worker process)."""
+    params, chunk = task
+    from oracle import deposit as od
+    from oracle.deposit import OracleGrid
+    og = OracleGrid.from_params(params)
+    return od.deposit(og, [chunk["x"], chunk["y"], chunk["z"]],
+                      [chunk["ux"], chunk["uy"], chunk["uz"]], chunk["w"])
+
+
+def oracle_J_all_cores(params, arrays, procs, chunk=1 << 20):
+    """J of the FP64 oracle for all particles: fixed chunks of `chunk` particles deposited
+    in `procs` worker processes, the per-chunk grids summed in chunk order (deterministic).
+    Returns (J, seconds, chunks)."""
+    import multiprocessing as mp
+    N = arrays["x"].size
+    keys = ("x", "y", "z", "ux", "uy", "uz", "w")
+    tasks = [(params, {k: arrays[k][i:i + chunk] for k in keys}) for i in range(0, N, chunk)]
+    ctx = mp.get_context("spawn")      # workers never inherit the GPU context
+    with ctx.Pool(procs) as pool:
+        pool.map(int, range(procs))    # workers started before the clock
+        t0 = time.perf_counter()
+        total = None
+        for J in pool.imap(_oracle_chunk, tasks):
+            total = J if total is None else [a + b for a, b in zip(total, J)]
+        dt = time.perf_counter() - t0
+    return total, dt, len(tasks)
+
+
+def _valid_host_arrays(parts):
+    host = parts.to_numpy()
+    valid = host["id"] != -1
+    return {k: np.ascontiguousarray(v[valid]) for k, v in host.items()}
+
+
+def full_size_check(pic, torch, grid, parts, bins, J, path, params, procs):
+    """One more deposition of the full workload after the timed steps (same path and
+    tiles, J overwritten, no drift), compared per component with the FP64 oracle over
+    every particle (all host cores). Returns (result, oracle seconds)."""
+    pic.deposit(grid, parts, bins, path, 0, J=J)
+    torch.cuda.synchronize()
+    got = [j.cpu().numpy() for j in J]
+    arrays = _valid_host_arrays(parts)
+    want, dt, nch = oracle_J_all_cores(params, arrays, procs)
+    errs = [float(np.linalg.norm(got[c] - want[c]) / np.linalg.norm(want[c])) for c in range(3)]
+    return {"rel_l2_full_size": max(errs), "rel_l2_per_component": errs,
+            "particles": int(arrays["x"].size), "oracle_s": dt, "oracle_procs": procs,
+            "oracle_chunks": nch}, dt
 
 
 def _events_ms(torch, fn, reps):
@@ -600,9 +692,10 @@ def _cpu_model():
     return "unknown"
 
 
-def cpu_baseline(sample):
-    """The FP64 oracle (as written, untuned) on the first `sample` particles of the
-    workload, one process on the host."""
+def cpu_baseline(sample, N, full_s, procs):
+    """The FP64 oracle (as written, untuned) timed on the host: (a) the first `sample`
+    particles of the workload in one process; (b) all N particles of the full-size check
+    on `procs` worker processes (fixed chunks, grids summed in chunk order)."""
     from paper_2601_08277_amd import synth
     from oracle import deposit as od
     from oracle.deposit import OracleGrid
@@ -614,10 +707,79 @@ def cpu_baseline(sample):
     od.deposit(og, [arrays["x"][sl], arrays["y"][sl], arrays["z"][sl]],
                [arrays["ux"][sl], arrays["uy"][sl], arrays["uz"][sl]], arrays["w"][sl])
     dt = time.perf_counter() - t0
-    return {"value": sample / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample} particles of the 128^3 x 8 workload, full grid, "
-                      f"FP64 NumPy stencil oracle, one process ({dt:.1f} s)",
-            "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+    one = {"value": sample / dt, "unit": "particles/s", "cores": 1,
+           "sample": f"first {sample} particles of the 128^3 x 8 workload, full grid ({dt:.1f} s)"}
+    return {"value": N / full_s, "unit": "particles/s", "cores": procs, "kind": "oracle",
+            "sample": f"all {N} particles of the 128^3 x 8 workload after the timed steps, "
+                      f"FP64 NumPy stencil oracle in {procs} processes, 2^20-particle chunks "
+                      f"summed in chunk order ({full_s:.1f} s)",
+            "one_process": one, "host_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+
+
+def _slab_oracle(params, arrays, za, zb, procs):
+    """Oracle J on z-node planes [za, zb) of a grid that is guard-bounded in z, from the
+    particles whose stencils reach those planes (cells za - 2 .. zb + 1, order 3) deposited
+    on a guard-bounded sub-grid. Returns (planes of the three components, particles)."""
+    n = params["n"]
+    ng = params["ng"]
+    lo, hi = max(0, za - 2), min(n[2], zb + 2)
+    sel = (arrays["z"] >= lo) & (arrays["z"] < hi)
+    sub = {k: np.ascontiguousarray(v[sel]) for k, v in arrays.items()}
+    sp = dict(params, n=(n[0], n[1], hi - lo), x0=(0.0, 0.0, float(lo)))
+    J, _, _ = oracle_J_all_cores(sp, sub, procs)
+    return [j[za - lo + ng: zb - lo + ng] for j in J], int(sel.sum())
+
+
+def c3_leg(args, torch, pic, synth, procs):
+    """The 256x256x1024 laser-wakefield-shaped snapshot (order 3): static deposition on every
+    path (J overwritten), the best path's roofline fraction, and its rel-L2 against the FP64
+    oracle on two slabs of z planes (the lower guard boundary and a slab through the
+    sheath and bubble), where the oracle is exact from the particles that reach them."""
+    params, arrays = synth.c3()
+    N = arrays["x"].size
+    grid = pic.Grid(params)
+    n = params["n"]
+    ncell = int(np.prod(n))
+    ng = params["ng"]
+    slabs = [(-2, 14), (700, 732)]
+    log(f"  {N} particles generated; oracle on z-plane slabs {slabs}")
+    refs = [_slab_oracle(params, arrays, za, zb, procs) for za, zb in slabs]
+    slots = pic.slots_for(N, ncell, 0.25)
+    parts = pic.Particles.from_arrays(arrays, slots)
+    del arrays
+    tile = tuple(int(t) for t in args.tile.split("x"))
+    bins = pic.Bins(grid, tile, 0.25, slots)
+    pic.rebin(grid, parts, bins, pic.REBIN_FULL)
+    J = pic.new_J(grid)
+    res = {}
+    byts = N * 40 + ncell * 12
+    for name in ("cell_valu", "mfma_bf16", "mfma_fp16", "atomic"):
+        log(f"  path {name}")
+        reps = 10 if name == "cell_valu" else 3
+        ms = _events_ms(torch, lambda: pic.deposit(grid, parts, bins, name, 0, J=J), reps)
+        torch.cuda.synchronize()
+        errs = []
+        for (za, zb), (want, _) in zip(slabs, refs):
+            for c in range(3):
+                got = J[c][za + ng: zb + ng].cpu().numpy()
+                errs.append(float(np.linalg.norm(got - want[c]) / np.linalg.norm(want[c])))
+        res[name] = {"kernel_ms": ms, "particles_per_s": N / (ms * 1e-3),
+                     "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "rel_l2_vs_oracle_z_slabs": max(errs)}
+    bins.check()
+    bins.close()
+    best = min(res, key=lambda k: res[k]["kernel_ms"])
+    ms = res[best]["kernel_ms"]
+    return {"workload": "LWFA-shaped 256x256x1024, order 3, periodic x/y, guard z (ng 3); "
+                        "static deposition, J overwritten", "particles": int(N), "cells": ncell,
+            "tile": list(tile), "path": best, "particles_per_s": N / (ms * 1e-3), "kernel_ms": ms,
+            "roofline": {"bound": "hbm", "achieved": byts / (ms * 1e-3) / 1e9,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "bytes_per_launch": byts, "bytes_basis": "40 B per particle + 12 B per cell"},
+            "rel_l2_slabs": {"z_planes": slabs, "particles": [r[1] for r in refs],
+                             "rel_l2": res[best]["rel_l2_vs_oracle_z_slabs"]},
+            "paths": res}
 
 
 if __name__ == "__main__":

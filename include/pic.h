@@ -137,7 +137,8 @@ typedef struct {
 void pic_sort_policy_default(pic_sort_policy* out);
 
 /* Host-side policy decision of Sec. 4.4 (prioritised triggers 1..5); returns 1 to run a
- * global sort. `trigger` (nullable) receives the deciding rule number, 0 if none. */
+ * global sort. `trigger` (nullable) receives the deciding rule number, 0 if none. A
+ * negative empty_slot_ratio means "not known yet" and skips trigger 4. */
 int pic_policy_decide(const pic_sort_policy* p, int steps_since_sort, int rebuilds_since_sort,
                       double empty_slot_ratio, double perf, double perf_baseline, int* trigger);
 
@@ -173,14 +174,45 @@ pic_status pic_bins_copy_tables(const pic_bins* bins, int32_t* off_host, int32_t
  * uniform gaps. Uses the mover list of the last pic_deposit(PIC_F_EMIT_MOVERS) when it
  * is fresh, otherwise scans all particles first. A mover that finds no slot stays in its
  * old bin (deposition still handles it correctly) and is retried next time. AUTO:
- * INCREMENTAL unless the policy (evaluated on the statistics of an earlier call, without
- * synchronising) asks for FULL. Particle payload moves between slots; ids travel with it.
- * `policy` may be NULL (defaults). */
+ * INCREMENTAL unless the policy asks for FULL; the policy reads the statistics of the
+ * calls up to PIC_POLICY_LAG calls back (waiting for the copy of call s - 2 if it has not
+ * landed; the stream is not synchronised). Particle payload moves between slots; ids
+ * travel with it. `policy` may be NULL (defaults). Not capturable into a graph: refused
+ * (UNSUPPORTED) while `stream` is capturing. */
 pic_status pic_rebin(const pic_grid* grid, pic_particles* p, pic_bins* bins, int mode,
                      const pic_sort_policy* policy, hipStream_t stream);
 
 /* Synchronises `stream` and returns the statistics of the last pic_rebin. */
 pic_status pic_rebin_stats_read(pic_bins* bins, hipStream_t stream, pic_rebin_stats* out);
+
+/* One rebin call as the bins recorded it: what the policy (Alg. 1, "Global Sort
+ * Decision"; Sec. 4.4) saw and decided, then the call's own statistics. Calls are numbered
+ * from 0 (the first FULL) per bins object. The decision of call s sees the statistics of
+ * calls up to s - 2 only (PIC_POLICY_LAG): pic_rebin waits for those if they have not come
+ * back yet, so the host runs at most two rebins ahead of the device and the decisions do
+ * not depend on timing. */
+#define PIC_POLICY_LAG 2
+typedef struct {
+  int64_t seq;                  /* call number                                          */
+  int32_t mode;                 /* executed: PIC_REBIN_FULL or PIC_REBIN_INCREMENTAL     */
+  int32_t trigger;              /* AUTO: deciding rule 0..5 (0: none fired); -1 explicit */
+  int32_t steps_since_sort;     /* policy inputs at the decision                         */
+  int32_t rebuilds_since_sort;  /*   local rebuilds of calls after the last FULL, <= s-2 */
+  double known_empty_ratio;     /*   empty-slot ratio of call s-2 (-1: before the FULL)  */
+  int64_t n_valid;              /* statistics of this call (valid once `complete`)       */
+  int64_t n_moved, n_overflow, n_mover_drop;
+  int32_t n_local_rebuilds;
+  uint32_t error_flags;
+  double empty_slot_ratio;
+  int32_t complete;             /* 1 once the statistics have come back                  */
+  int32_t pad;
+} pic_rebin_record;
+
+/* Synchronises `stream` and copies the records of calls first .. first + max - 1 (those
+ * still kept: the newest 65,536 calls) to `out` (host array of `max`); *count receives the
+ * number copied. Errors: INVALID_ARG (NULL pointers, negative first or max). */
+pic_status pic_rebin_history(pic_bins* bins, hipStream_t stream, int64_t first, int32_t max,
+                             pic_rebin_record* out, int32_t* count);
 
 /* Optional performance sample for policy trigger 5 (higher is better, e.g. particles/s). */
 pic_status pic_bins_report_perf(pic_bins* bins, double perf);

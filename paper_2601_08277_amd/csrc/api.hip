@@ -2,6 +2,7 @@
 // global re-sort policy (Sec. 4.4). Kernels live in deposit.hip, rebin.hip, backward.hip.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -136,7 +137,8 @@ extern "C" int pic_policy_decide(const pic_sort_policy* p, int steps_since_sort,
   } else if (rebuilds_since_sort > p->rebuild_count) {
     t = 3;
     decide = 1;
-  } else if (empty_slot_ratio < p->empty_ratio || empty_slot_ratio > p->full_ratio) {
+  } else if (empty_slot_ratio >= 0.0 &&
+             (empty_slot_ratio < p->empty_ratio || empty_slot_ratio > p->full_ratio)) {
     t = 4;
     decide = 1;
   } else if (p->perf_enable && perf > 0.0 && perf_baseline > 0.0 &&
@@ -164,7 +166,8 @@ static void free_bins(pic_bins* b) {
   for (void* p : sp)
     if (p) (void)hipFree(p);
   if (b->hstats) (void)hipHostFree(b->hstats);
-  if (b->stats_ev) (void)hipEventDestroy(b->stats_ev);
+  for (hipEvent_t ev : b->stats_ev)
+    if (ev) (void)hipEventDestroy(ev);
   delete b;
 }
 
@@ -259,8 +262,8 @@ extern "C" pic_status pic_bins_create(const pic_grid* grid, const int tile[3], d
     A(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     if (lds > 0) b->max_lds = (size_t)lds;
   }
-  A(hipHostMalloc((void**)&b->hstats, sizeof(CtrBlock), hipHostMallocDefault));
-  A(hipEventCreateWithFlags(&b->stats_ev, hipEventDisableTiming));
+  A(hipHostMalloc((void**)&b->hstats, sizeof(CtrBlock) * STATS_RING, hipHostMallocDefault));
+  for (hipEvent_t& ev : b->stats_ev) A(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   if (e != hipSuccess) {
     free_bins(b);
     return check_hip(e, "pic_bins_create allocation");
@@ -280,7 +283,7 @@ extern "C" pic_status pic_bins_create(const pic_grid* grid, const int tile[3], d
   A(hipMemset(b->kb.ins_cnt, 0, (size_t)nbins * sizeof(int32_t)));
   A(hipMemset(b->kb.tile_flag, 0, (size_t)ntiles * sizeof(int32_t)));
   A(hipMemset(b->dctr, 0, sizeof(CtrBlock)));
-  memset(b->hstats, 0, sizeof(CtrBlock));
+  memset(b->hstats, 0, sizeof(CtrBlock) * STATS_RING);
   A(hipDeviceSynchronize());
   if (e != hipSuccess) {
     free_bins(b);
@@ -319,17 +322,42 @@ extern "C" pic_status pic_bins_copy_tables(const pic_bins* b, int32_t* off_host,
   return PIC_OK;
 }
 
-// Consume the statistics of an earlier rebin if their copy has landed (no sync).
-static void consume_stats(pic_bins* b) {
-  if (!b->stats_pending) return;
-  if (hipEventQuery(b->stats_ev) != hipSuccess) return;
-  b->stats_pending = false;
-  if (b->seq_consumed >= b->seq_enqueued) return;
-  b->seq_consumed = b->seq_enqueued;
-  const CtrBlock& c = *b->hstats;
-  b->rebuilds_since_sort += c.ctr[CTR_NREB];
-  double cap = (double)c.cap_used;
-  b->last_empty_ratio = cap > 0 ? 1.0 - (double)c.ctr[CTR_NVALID] / cap : 0.0;
+static double empty_ratio_of(const CtrBlock& c) {
+  const double cap = (double)c.cap_used;
+  return cap > 0 ? 1.0 - (double)c.ctr[CTR_NVALID] / cap : 0.0;
+}
+
+static pic_rebin_record* record_of(pic_bins* b, int64_t seq) {
+  if (seq < b->history_base || seq >= b->history_base + (int64_t)b->history.size()) return nullptr;
+  return &b->history[(size_t)(seq - b->history_base)];
+}
+
+// Read the statistics of every call up to `upto` (in call order), waiting for each copy to
+// land, and fold them into the policy state: local rebuilds of calls after the last full
+// sort add up; the empty-slot ratio is that of the newest such call (the full sort's own
+// statistics included).
+static pic_status consume_stats(pic_bins* b, int64_t upto) {
+  upto = std::min(upto, b->seq_enqueued - 1);
+  while (b->seq_consumed <= upto) {
+    const int64_t j = b->seq_consumed;
+    const int slot = (int)(j % STATS_RING);
+    HIP_TRY(hipEventSynchronize(b->stats_ev[slot]));
+    const CtrBlock& c = b->hstats[slot];
+    if (j > b->last_full_seq) b->rebuilds_since_sort += c.ctr[CTR_NREB];
+    if (j >= b->last_full_seq) b->known_empty_ratio = empty_ratio_of(c);
+    if (pic_rebin_record* r = record_of(b, j)) {
+      r->n_valid = c.ctr[CTR_NVALID];
+      r->n_moved = c.ctr[CTR_NMOV_LAST];
+      r->n_overflow = c.ctr[CTR_NOVF];
+      r->n_mover_drop = c.ctr[CTR_NDROP];
+      r->n_local_rebuilds = c.ctr[CTR_NREB];
+      r->error_flags = c.err;
+      r->empty_slot_ratio = empty_ratio_of(c);
+      r->complete = 1;
+    }
+    b->seq_consumed = j + 1;
+  }
+  return PIC_OK;
 }
 
 extern "C" pic_status pic_bins_report_perf(pic_bins* b, double perf) {
@@ -354,15 +382,30 @@ extern "C" pic_status pic_rebin(const pic_grid* grid, pic_particles* p, pic_bins
     return set_error(PIC_ERR_INVALID_ARG, "unknown rebin mode");
   if (mode != PIC_REBIN_FULL && !b->sorted_once)
     return set_error(PIC_ERR_INVALID_ARG, "the first rebin must be PIC_REBIN_FULL");
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+      return set_error(PIC_ERR_UNSUPPORTED, "pic_rebin cannot be captured into a graph");
+  }
   KGrid G = make_kgrid(*grid);
   KPart P = make_kpart(*p);
+  const int64_t seq = b->seq_enqueued;
+  // statistics the decision may use (and ring slots about to be reused) come back first
+  if ((st = consume_stats(b, seq - POLICY_LAG)) != PIC_OK) return st;
+  pic_rebin_record rec{};
+  rec.seq = seq;
+  rec.trigger = -1;
+  rec.steps_since_sort = b->steps_since_sort;
+  rec.rebuilds_since_sort = b->rebuilds_since_sort;
+  rec.known_empty_ratio = b->known_empty_ratio;
   int run = mode;
   if (mode == PIC_REBIN_AUTO) {
-    consume_stats(b);
     int trig = 0;
     int dec = pic_policy_decide(policy, b->steps_since_sort, b->rebuilds_since_sort,
-                                b->last_empty_ratio, b->perf_last, b->perf_baseline, &trig);
+                                b->known_empty_ratio, b->perf_last, b->perf_baseline, &trig);
     b->last_decision = dec;
+    rec.trigger = trig;
     run = dec ? PIC_REBIN_FULL : PIC_REBIN_INCREMENTAL;
   }
   if (run == PIC_REBIN_FULL) {
@@ -370,20 +413,30 @@ extern "C" pic_status pic_rebin(const pic_grid* grid, pic_particles* p, pic_bins
     b->sorted_once = true;
     b->steps_since_sort = 0;
     b->rebuilds_since_sort = 0;
+    b->last_full_seq = seq;
+    b->known_empty_ratio = -1.0;
     b->n_global_sorts++;
     b->perf_baseline_pending = true;
   } else {
     rebin_incremental(b, G, P, stream);
     b->steps_since_sort++;
   }
+  rec.mode = run;
   b->movers_fresh = false;
   b->last_mode = run;
-  // statistics: device counters -> pinned host buffer, consumed later without a sync
+  if (b->history.size() >= HISTORY_MAX) {
+    b->history.pop_front();
+    b->history_base++;
+  }
+  if (b->history.empty()) b->history_base = seq;
+  b->history.push_back(rec);
+  // statistics: device counters -> this call's pinned ring slot, read later in call order
+  const int slot = (int)(seq % STATS_RING);
   rebin_finish(b, stream);
-  b->seq_enqueued++;
-  b->stats_pending = true;
-  HIP_TRY(hipMemcpyAsync(b->hstats, b->dctr, sizeof(CtrBlock), hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipEventRecord(b->stats_ev, stream));
+  HIP_TRY(hipMemcpyAsync(&b->hstats[slot], b->dctr, sizeof(CtrBlock), hipMemcpyDeviceToHost,
+                         stream));
+  HIP_TRY(hipEventRecord(b->stats_ev[slot], stream));
+  b->seq_enqueued = seq + 1;
   reset_step_counters(b, stream);
   return check_hip(hipGetLastError(), "pic_rebin launch");
 }
@@ -391,8 +444,9 @@ extern "C" pic_status pic_rebin(const pic_grid* grid, pic_particles* p, pic_bins
 extern "C" pic_status pic_rebin_stats_read(pic_bins* b, hipStream_t stream, pic_rebin_stats* out) {
   if (!b || !out) return set_error(PIC_ERR_INVALID_ARG, "NULL argument");
   HIP_TRY(hipStreamSynchronize(stream));
-  consume_stats(b);
-  const CtrBlock& c = *b->hstats;
+  pic_status st = consume_stats(b, b->seq_enqueued - 1);
+  if (st != PIC_OK) return st;
+  const CtrBlock& c = b->hstats[(int)((b->seq_enqueued + STATS_RING - 1) % STATS_RING)];
   out->n_valid = c.ctr[CTR_NVALID];
   out->n_moved = c.ctr[CTR_NMOV_LAST];
   out->n_overflow = c.ctr[CTR_NOVF];
@@ -406,6 +460,24 @@ extern "C" pic_status pic_rebin_stats_read(pic_bins* b, hipStream_t stream, pic_
       b->perf_baseline, nullptr);
   out->last_mode = b->last_mode;
   out->error_flags = c.err;
+  return PIC_OK;
+}
+
+extern "C" pic_status pic_rebin_history(pic_bins* b, hipStream_t stream, int64_t first,
+                                        int32_t max, pic_rebin_record* out, int32_t* count) {
+  if (!b || !count || (max > 0 && !out)) return set_error(PIC_ERR_INVALID_ARG, "NULL argument");
+  if (first < 0 || max < 0) return set_error(PIC_ERR_INVALID_ARG, "first and max must be >= 0");
+  *count = 0;
+  HIP_TRY(hipStreamSynchronize(stream));
+  pic_status st = consume_stats(b, b->seq_enqueued - 1);
+  if (st != PIC_OK) return st;
+  int32_t n = 0;
+  for (int64_t q = std::max(first, b->history_base); n < max; ++q) {
+    const pic_rebin_record* r = record_of(b, q);
+    if (!r) break;
+    out[n++] = *r;
+  }
+  *count = n;
   return PIC_OK;
 }
 

@@ -1,6 +1,7 @@
 // Host-side state of libpic objects and the launchers each kernel file provides.
 #pragma once
 
+#include <deque>
 #include <string>
 
 #include "pic_internal.h"
@@ -14,6 +15,15 @@ struct CtrBlock {
   unsigned long long desired; // full sort: extra slots wanted
   unsigned long long pad;
 };
+
+// Statistics of rebin calls come back through a ring of pinned counter blocks, one per
+// call. The policy of call s reads the statistics of every call up to s - POLICY_LAG,
+// waiting for them if they have not landed, so its decisions do not depend on how far
+// the host runs ahead of the device (it runs at most POLICY_LAG rebins ahead).
+constexpr int STATS_RING = 8;
+constexpr int POLICY_LAG = 2;
+static_assert(STATS_RING > POLICY_LAG, "a ring slot is reused only after it was consumed");
+constexpr size_t HISTORY_MAX = 1u << 16;   // rebin records kept per bins object
 
 struct pic_bins {
   pic_grid grid;
@@ -33,20 +43,24 @@ struct pic_bins {
   // host-side state
   bool movers_fresh = false;
   bool sorted_once = false;
-  CtrBlock* hstats = nullptr;       // pinned
-  hipEvent_t stats_ev = nullptr;
-  bool stats_pending = false;
-  int64_t seq_enqueued = 0, seq_consumed = 0;
+  CtrBlock* hstats = nullptr;       // pinned ring, STATS_RING blocks
+  hipEvent_t stats_ev[STATS_RING] = {};
+  int64_t seq_enqueued = 0;         // rebin calls whose statistics copy was enqueued
+  int64_t seq_consumed = 0;         // calls whose statistics the host has read
   int last_mode = -1;
-  // policy state (Sec. 4.4)
+  // policy state (Sec. 4.4), as known to the host after consuming statistics
   int steps_since_sort = 0;
   int rebuilds_since_sort = 0;
   int n_global_sorts = 0;
-  double last_empty_ratio = 0.0;
+  int64_t last_full_seq = -1;       // call number of the last full sort
+  double known_empty_ratio = -1.0;  // of the newest consumed call since that sort; -1 unknown
   int last_decision = 0;
   double perf_baseline = -1.0;
   double perf_last = -1.0;
   bool perf_baseline_pending = true;
+  // per-call records (decision inputs, then the statistics once consumed)
+  std::deque<pic_rebin_record> history;
+  int64_t history_base = 0;         // seq of history.front()
 };
 
 // Zero fill of int32 device memory (rebin.hip).

@@ -23,7 +23,8 @@ F_ACCUMULATE, F_DETERMINISTIC, F_EMIT_MOVERS, F_DRIFT, F_MIDPOINT = 1, 2, 4, 8, 
 INVALID_ID = -1
 
 EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "pic_bins_destroy",
-           "pic_bins_get_view", "pic_bins_copy_tables", "pic_rebin", "pic_rebin_stats_read", "pic_bins_report_perf",
+           "pic_bins_get_view", "pic_bins_copy_tables", "pic_rebin", "pic_rebin_stats_read",
+           "pic_rebin_history", "pic_bins_report_perf",
            "pic_deposit", "pic_deposit_rho", "pic_gather_fields", "pic_deposit_backward",
            "pic_drift", "pic_push", "pic_deposit_esirkepov",
            "pic_plan_create",
@@ -64,6 +65,19 @@ class PicRebinStats(ctypes.Structure):
                 ("last_mode", ctypes.c_int32), ("error_flags", ctypes.c_uint32)]
 
 
+class PicRebinRecord(ctypes.Structure):
+    _fields_ = [("seq", ctypes.c_int64), ("mode", ctypes.c_int32), ("trigger", ctypes.c_int32),
+                ("steps_since_sort", ctypes.c_int32), ("rebuilds_since_sort", ctypes.c_int32),
+                ("known_empty_ratio", ctypes.c_double), ("n_valid", ctypes.c_int64),
+                ("n_moved", ctypes.c_int64), ("n_overflow", ctypes.c_int64),
+                ("n_mover_drop", ctypes.c_int64), ("n_local_rebuilds", ctypes.c_int32),
+                ("error_flags", ctypes.c_uint32), ("empty_slot_ratio", ctypes.c_double),
+                ("complete", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+POLICY_LAG = 2
+
+
 class PicBinsView(ctypes.Structure):
     _fields_ = [("nbins", ctypes.c_int64), ("ntiles", ctypes.c_int64), ("ntile", ctypes.c_int32 * 3),
                 ("off", ctypes.c_void_p), ("len", ctypes.c_void_p), ("bin_cell", ctypes.c_void_p)]
@@ -93,6 +107,8 @@ def lib():
     L.pic_bins_copy_tables.argtypes = [vp, vp, vp, vp, vp]
     L.pic_rebin.argtypes = [P(PicGrid), P(PicParticles), vp, i32, P(PicSortPolicy), vp]
     L.pic_rebin_stats_read.argtypes = [vp, vp, P(PicRebinStats)]
+    L.pic_rebin_history.argtypes = [vp, vp, i64, ctypes.c_int32, P(PicRebinRecord),
+                                    P(ctypes.c_int32)]
     L.pic_bins_report_perf.argtypes = [vp, dbl]
     L.pic_deposit.argtypes = [P(PicGrid), P(PicParticles), vp, vp, vp, vp, i32, u32, vp]
     L.pic_deposit_backward.argtypes = [P(PicGrid), P(PicParticles), vp, vp, vp, vp, vp, vp, vp,
@@ -167,6 +183,7 @@ class Particles:
 
     def __init__(self, nslots, device="cuda"):
         self.nslots = int(nslots)
+        self.generation = 0    # bumped by every binding call that moves or rewrites slots
         for name, dt in self.FIELDS:
             fill = INVALID_ID if name == "id" else 0
             setattr(self, name, torch.full((self.nslots,), fill, dtype=dt, device=device))
@@ -238,6 +255,15 @@ class Bins:
         _check(lib().pic_rebin_stats_read(self.h, _stream(), ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in PicRebinStats._fields_}
 
+    def history(self, first=0, max_records=1 << 16):
+        """Per-call rebin records (pic_rebin_history) as a list of dicts (synchronises)."""
+        buf = (PicRebinRecord * max_records)()
+        n = ctypes.c_int32(0)
+        _check(lib().pic_rebin_history(self.h, _stream(), int(first), int(max_records), buf,
+                                       ctypes.byref(n)))
+        return [{k: getattr(buf[i], k) for k, _ in PicRebinRecord._fields_ if k != "pad"}
+                for i in range(n.value)]
+
     def check(self):
         _check(lib().pic_check(self.h, _stream()))
 
@@ -265,6 +291,7 @@ def policy_decide(steps, rebuilds, empty_ratio, perf=0.0, base=0.0, pol=None):
 
 
 def rebin(grid, parts, bins, mode=REBIN_INCREMENTAL, pol=None):
+    parts.generation += 1
     pc = parts.c()
     _check(lib().pic_rebin(ctypes.byref(grid.c), ctypes.byref(pc), bins.h, mode,
                            ctypes.byref(pol) if pol is not None else None, _stream()))
@@ -279,6 +306,8 @@ def deposit(grid, parts, bins, path=PATH_AUTO, flags=0, J=None):
         path = PATH_NAMES[path]
     if J is None:
         J = new_J(grid)
+    if flags & F_DRIFT:
+        parts.generation += 1
     pc = parts.c()
     _check(lib().pic_deposit(ctypes.byref(grid.c), ctypes.byref(pc), bins.h if bins else None,
                              _ptr(J[0]), _ptr(J[1]), _ptr(J[2]), path, flags, _stream()))
@@ -326,6 +355,9 @@ def deposit_batched(plan, parts_list, J_list=None, path=PATH_AUTO, flags=0):
     n = len(parts_list)
     if J_list is None:
         J_list = [new_J(g) for g in plan.grids]
+    if flags & F_DRIFT:
+        for p in parts_list:
+            p.generation += 1
     parr = (PicParticles * n)(*[p.c() for p in parts_list])
     jarr = (ctypes.c_void_p * (3 * n))(*[J[c].data_ptr() for J in J_list for c in range(3)])
     _check(lib().pic_deposit_batched(plan.h, parr, jarr, path, flags, _stream()))
@@ -358,6 +390,7 @@ def gather_fields(grid, parts, bins, E, B):
 def push(grid, parts, bins, E, B, qm, dt):
     """Boris push in place (pic_push): gather E, B, rotate u, move x by dt."""
     F = [f.contiguous() for f in list(E) + list(B)]
+    parts.generation += 1
     pc = parts.c()
     _check(lib().pic_push(ctypes.byref(grid.c), ctypes.byref(pc), bins.h if bins else None,
                           *[_ptr(f) for f in F], float(qm), float(dt), 0, _stream()))
@@ -393,6 +426,7 @@ def deposit_backward(grid, parts, bins, G, want_dw=True):
 
 
 def drift(grid, parts, dt):
+    parts.generation += 1
     pc = parts.c()
     _check(lib().pic_drift(ctypes.byref(grid.c), ctypes.byref(pc), float(dt), _stream()))
 
@@ -402,16 +436,28 @@ class PicDeposit(torch.autograd.Function):
 
     The forward saves only its inputs; shape weights are recomputed in the backward kernel.
     The particle tensors are those of a Particles object (`parts`), whose id array marks gaps.
+    The backward reads the particles as they are when it runs, so it refuses to run after
+    any call that moved or rewrote them (rebin, drift, push, a drifting deposit) or after an
+    in-place change of the tensors: it would return gradients for other positions or another
+    slot order.
     """
+
+    @staticmethod
+    def _stamp(parts):
+        return (parts.generation,) + tuple(getattr(parts, n)._version for n, _ in Particles.FIELDS)
 
     @staticmethod
     def forward(ctx, x, y, z, ux, uy, uz, w, grid, parts, bins, path):
         ctx.grid, ctx.parts, ctx.bins = grid, parts, bins
         J = deposit(grid, parts, bins, path)
+        ctx.stamp = PicDeposit._stamp(parts)
         return tuple(J)
 
     @staticmethod
     def backward(ctx, gJx, gJy, gJz):
+        if PicDeposit._stamp(ctx.parts) != ctx.stamp:
+            raise RuntimeError("PicDeposit.backward: the particles were moved or changed "
+                               "after the forward; run the forward again")
         g = deposit_backward(ctx.grid, ctx.parts, ctx.bins, [gJx, gJy, gJz])
         dz = g["dz"].double() if ctx.grid.dim == 3 else torch.zeros_like(ctx.parts.z)
         return (g["dx"].double(), g["dy"].double(), dz, g["dux"], g["duy"], g["duz"], g["dw"],

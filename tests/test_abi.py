@@ -50,12 +50,13 @@ def test_binding_lists_every_symbol():
     (3, 500, 0.01, 0.1, 1.0), (50, 0, 0.25, 0.0, 0.0), (20, 101, 0.25, 0.0, 0.0),
     (20, 100, 0.25, 0.0, 0.0), (20, 0, 0.10, 0.0, 0.0), (20, 0, 0.90, 0.0, 0.0),
     (20, 0, 0.25, 0.7, 1.0), (20, 0, 0.25, 0.85, 1.0), (10, 0, 0.5, 0.0, 0.0),
-    (49, 0, 0.15, 0.0, 0.0), (49, 0, 0.85, 0.0, 0.0)])
+    (49, 0, 0.15, 0.0, 0.0), (49, 0, 0.85, 0.0, 0.0), (20, 0, -1.0, 0.0, 0.0),
+    (20, 101, -1.0, 0.0, 0.0)])
 def test_policy_matches_oracle(L, case):
     from paper_2601_08277_amd import pic
     steps, reb, empty, perf, base = case
-    want = ob.should_global_sort(steps, reb, empty, perf if perf > 0 else None,
-                                 base if base > 0 else None)
+    want = ob.should_global_sort(steps, reb, empty if empty >= 0 else None,
+                                 perf if perf > 0 else None, base if base > 0 else None)
     assert pic.policy_decide(steps, reb, empty, perf, base) == want
 
 

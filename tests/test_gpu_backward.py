@@ -129,3 +129,27 @@ def test_backward_with_stale_bins_and_without_bins(with_bins):
         assert np.all(got[k][~valid] == 0)
     bins.check()
     bins.close()
+
+
+def test_autograd_refuses_moved_particles():
+    """The backward recomputes weights from the particles as they are when it runs, so a
+    rebin (or any move) between forward and backward must raise instead of returning
+    gradients of other positions; without a move the backward runs."""
+    say("case autograd stale particles")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.c2(n=(16, 16, 16))
+    grid, og, parts, bins = setup(params, arrays)
+    G = [torch.from_numpy(g).cuda() for g in synth.adjoint_field(grid.shape)]
+    parts.x.requires_grad_(True)
+    J = pic.deposit_autograd(grid, parts, bins, pic.PATH_CELL_VALU)
+    loss = sum((J[c] * G[c]).sum() for c in range(3))
+    loss.backward()
+    assert parts.x.grad is not None
+    parts.x.grad = None
+    J = pic.deposit_autograd(grid, parts, bins, pic.PATH_CELL_VALU)
+    loss = sum((J[c] * G[c]).sum() for c in range(3))
+    pic.drift(grid, parts, params["dt"])
+    with pytest.raises(RuntimeError, match="moved or changed"):
+        loss.backward()
+    parts.x.requires_grad_(False)
+    bins.close()

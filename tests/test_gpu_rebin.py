@@ -206,3 +206,110 @@ def test_mover_list_capacity_drop_is_retried():
     off, ln, bc = bins.tables()
     check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref)
     bins.close()
+
+
+def _replay_policy(hist, pol, lag):
+    """The oracle's decisions for calls 1.. of a history whose call 0 is the initial FULL:
+    call s sees steps since the last sort exactly and the statistics of calls <= s - lag."""
+    last_full = 0
+    want = []
+    for s in range(1, len(hist)):
+        steps = s - last_full - 1
+        rebuilds = sum(hist[j]["n_local_rebuilds"] for j in range(last_full + 1, s - lag + 1))
+        ratio = hist[s - lag]["empty_slot_ratio"] if s - lag >= last_full else None
+        dec, trig = ob.should_global_sort(steps, rebuilds, ratio, policy=pol)
+        want.append((dec, trig))
+        if dec:
+            last_full = s
+    return want
+
+
+@pytest.mark.parametrize("which", ["rebuilds", "empty_ratio"])
+def test_auto_policy_pipelined(which):
+    """AUTO rebins enqueued back to back with no host synchronisation in the loop: every
+    call's decision equals the oracle policy replayed over the per-call statistics with the
+    stated lag, and global sorts fire from trigger 3 (local rebuilds, tight slack) or
+    trigger 4 (empty-slot ratio). After the loop J, positions and bins match the oracle."""
+    say(f"case auto-policy pipelined {which}")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.uniform(3, (32, 32, 24), 8, 0.3, 3, seed=31, dt=0.5)
+    slack = 0.1 if which == "rebuilds" else 0.3
+    grid, og, parts, bins = setup(params, arrays, tile=(8, 8, 4), slack=slack,
+                                  max_movers=1 << 20)
+    if which == "rebuilds":
+        pd = dict(min_interval=3, interval=1000, rebuild_count=40, empty_ratio=0.0,
+                  full_ratio=1.0, perf_enable=0)
+    else:
+        pd = dict(min_interval=4, interval=1000, rebuild_count=1 << 30, empty_ratio=0.3,
+                  full_ratio=1.0, perf_enable=0)
+    pol = pic.policy(**pd)
+    J = pic.new_J(grid)
+    steps = 32
+    ref = dict(arrays)
+    torch.cuda.synchronize()
+    for _ in range(steps - 1):
+        pic.deposit(grid, parts, bins, "cell_valu", pic.F_DRIFT | pic.F_EMIT_MOVERS, J=J)
+        pic.rebin(grid, parts, bins, pic.REBIN_AUTO, pol)
+        ref = _advance_oracle(og, ref, params["dt"])
+    want_J = oracle_J(og, ref)
+    pic.deposit(grid, parts, bins, "cell_valu", pic.F_DRIFT | pic.F_EMIT_MOVERS, J=J)
+    pic.rebin(grid, parts, bins, pic.REBIN_AUTO, pol)
+    ref = _advance_oracle(og, ref, params["dt"])
+    hist = bins.history()
+    assert len(hist) == steps + 1 and all(h["complete"] for h in hist)
+    assert [h["seq"] for h in hist] == list(range(steps + 1))
+    want = _replay_policy(hist, pd, pic.POLICY_LAG)
+    got = [(h["mode"] == pic.REBIN_FULL, h["trigger"]) for h in hist[1:]]
+    fulls = [s + 1 for s, (d, _) in enumerate(want) if d]
+    say(f"full sorts at calls {fulls}; rebuilds per call "
+        f"{[h['n_local_rebuilds'] for h in hist[1:9]]}...")
+    assert got == want
+    trig = 3 if which == "rebuilds" else 4
+    assert sum(1 for d, t in want if d and t == trig) >= 3, want
+    assert sum(h["n_local_rebuilds"] for h in hist) > 0 or which == "empty_ratio"
+    errs = [rel_l2(J[c].cpu().numpy(), want_J[c]) for c in range(3)]
+    assert max(errs) <= TOL_FP32, errs
+    off, ln, bc = bins.tables()
+    last = hist[-1]
+    stale = check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref,
+                       stale_ok=int(last["n_overflow"] + last["n_mover_drop"]))
+    assert stale <= last["n_overflow"] + last["n_mover_drop"]
+    bins.check()
+    bins.close()
+
+
+def test_timed_step_configuration():
+    """The benchmark's step exactly: per-cell VALU path, PIC_F_DRIFT | PIC_F_EMIT_MOVERS
+    (no midpoint), 8x8x4 tiles, slack 0.5, AUTO rebins, on a grid with ragged tiles. Every
+    step: J within the float32 tolerance of the oracle, positions bitwise equal to the
+    oracle's drift, bins equal to the oracle's sets (stale particles only where an insert
+    overflowed)."""
+    say("case timed-step configuration")
+    from paper_2601_08277_amd import pic
+    params, arrays = synth.uniform(3, (36, 28, 30), 8, 0.05, 3, seed=1002, dt=0.2)
+    grid, og, parts, bins = setup(params, arrays, tile=(8, 8, 4), slack=0.5)
+    pol = pic.policy()
+    J = pic.new_J(grid)
+    ref = dict(arrays)
+    for step in range(6):
+        want = oracle_J(og, ref)
+        for j in J:
+            j.zero_()
+        pic.deposit(grid, parts, bins, "auto", pic.F_DRIFT | pic.F_EMIT_MOVERS, J=J)
+        errs = [rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)]
+        assert max(errs) <= TOL_FP32, (step, errs)
+        ref = _advance_oracle(og, ref, params["dt"])
+        host = _host(parts)
+        valid = host["id"] != -1
+        order = np.argsort(host["id"][valid])
+        for k in "xyz":
+            got = host[k][valid][order]
+            assert np.array_equal(got.view(np.uint64), ref[k].view(np.uint64)), (step, k)
+        pic.rebin(grid, parts, bins, pic.REBIN_AUTO, pol)
+        st = bins.stats()
+        off, ln, bc = bins.tables()
+        stale = check_bins(og, _host(parts), off, ln, bc, ref_arrays=ref,
+                           stale_ok=int(st["n_overflow"] + st["n_mover_drop"]))
+        assert stale == st["n_overflow"] + st["n_mover_drop"], (step, st)
+        assert st["error_flags"] == 0
+    bins.close()
