@@ -230,6 +230,19 @@ pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bins* bins,
                        float* Jx, float* Jy, float* Jz, int path, unsigned flags,
                        hipStream_t stream);
 
+/* pic_deposit for callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): same arguments, checks, paths,
+ * flags and results as pic_deposit, but the per-tile stencil windows between the
+ * deposition kernel and the window sum live in one fixed 32 MiB device array of the
+ * library (one per GPU, held until the process ends) instead of the bins' allocation.
+ * Allocates nothing. Bins whose windows need more than 32 MiB (ntiles x 3 x wmax x 4 B,
+ * wmax = prod_d (tile_d + 4): 14 MB for 64^3 cells in 8x8x4 tiles, 113 MB for 128^3) are
+ * refused with PIC_ERR_INVALID_ARG before anything is enqueued. Every call on one GPU shares the array: calls that overlap on one
+ * GPU (other streams, other host threads) race. */
+pic_status pic_deposit_noalloc(const pic_grid* grid, pic_particles* p, pic_bins* bins,
+                               float* Jx, float* Jy, float* Jz, int path, unsigned flags,
+                               hipStream_t stream);
+
 /* Adjoint of pic_deposit for L = sum_c <G_c, J_c>. Writes per slot (gap slots get 0):
  * dL/dx, dL/dy, dL/dz (dz ignored in 2D; may be NULL there), dL/dux, dL/duy, dL/duz and,
  * if dw is not NULL, dL/dw. Shape weights are recomputed, not stored. `bins` may be NULL

@@ -481,9 +481,10 @@ extern "C" pic_status pic_rebin_history(pic_bins* b, hipStream_t stream, int64_t
   return PIC_OK;
 }
 
-extern "C" pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bins* b, float* Jx,
-                                  float* Jy, float* Jz, int path, unsigned flags,
-                                  hipStream_t stream) {
+// Argument checks of pic_deposit (and its no-allocation variant).
+pic_status deposit_check_args(const pic_grid* grid, const pic_particles* p, const pic_bins* b,
+                              const float* Jx, const float* Jy, const float* Jz, int path,
+                              unsigned flags) {
   pic_status st = validate_grid(grid);
   if (st != PIC_OK) return st;
   if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
@@ -506,16 +507,34 @@ extern "C" pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bi
   }
   if ((flags & (PIC_F_DRIFT | PIC_F_MIDPOINT)) && !std::isfinite(grid->dt))
     return set_error(PIC_ERR_INVALID_ARG, "dt must be finite");
+  return PIC_OK;
+}
+
+// Enqueue a checked deposition; the tile windows go to `wscr` (the bins' own when NULL).
+pic_status deposit_enqueue(const pic_grid* grid, pic_particles* p, pic_bins* b, float* Jx,
+                           float* Jy, float* Jz, int path, unsigned flags, float* wscr,
+                           hipStream_t stream) {
   KGrid G = make_kgrid(*grid);
   KPart P = make_kpart(*p);
-  if (!deposit_launch(G, P, path == PIC_PATH_UNSORTED ? nullptr : b, Jx, Jy, Jz, path, flags,
-                      grid->dt, stream))
-    return set_error(PIC_ERR_UNSUPPORTED, "deposition path not available for this grid");
+  pic_bins* bb = path == PIC_PATH_UNSORTED ? nullptr : b;
+  float* own = bb ? bb->kb.wscr : nullptr;
+  if (bb && wscr) bb->kb.wscr = wscr;      // kernels take the bins by value at launch
+  const bool ok = deposit_launch(G, P, bb, Jx, Jy, Jz, path, flags, grid->dt, stream);
+  if (bb) bb->kb.wscr = own;
+  if (!ok) return set_error(PIC_ERR_UNSUPPORTED, "deposition path not available for this grid");
   if (b) {
     if (flags & PIC_F_EMIT_MOVERS) b->movers_fresh = true;
     else if (flags & PIC_F_DRIFT) b->movers_fresh = false;
   }
   return check_hip(hipGetLastError(), "pic_deposit launch");
+}
+
+extern "C" pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bins* b, float* Jx,
+                                  float* Jy, float* Jz, int path, unsigned flags,
+                                  hipStream_t stream) {
+  pic_status st = deposit_check_args(grid, p, b, Jx, Jy, Jz, path, flags);
+  if (st != PIC_OK) return st;
+  return deposit_enqueue(grid, p, b, Jx, Jy, Jz, path, flags, nullptr, stream);
 }
 
 extern "C" pic_status pic_deposit_rho(const pic_grid* grid, const pic_particles* p, pic_bins* b,

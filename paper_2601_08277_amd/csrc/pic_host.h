@@ -87,6 +87,14 @@ pic_status validate_grid(const pic_grid* g);
 pic_status validate_particles(const pic_particles* p, int dim);
 bool same_grid(const pic_grid& a, const pic_grid& b);
 
+// pic_deposit's argument checks and launch, shared with its no-allocation variant (api.hip).
+pic_status deposit_check_args(const pic_grid* grid, const pic_particles* p, const pic_bins* b,
+                              const float* Jx, const float* Jy, const float* Jz, int path,
+                              unsigned flags);
+pic_status deposit_enqueue(const pic_grid* grid, pic_particles* p, pic_bins* b, float* Jx,
+                           float* Jy, float* Jz, int path, unsigned flags, float* wscr,
+                           hipStream_t stream);
+
 // Error reporting (api.hip).
 pic_status set_error(pic_status st, const std::string& msg);
 pic_status check_hip(hipError_t e, const char* what);

@@ -25,7 +25,7 @@ INVALID_ID = -1
 EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "pic_bins_destroy",
            "pic_bins_get_view", "pic_bins_copy_tables", "pic_rebin", "pic_rebin_stats_read",
            "pic_rebin_history", "pic_bins_report_perf",
-           "pic_deposit", "pic_deposit_rho", "pic_gather_fields", "pic_deposit_backward",
+           "pic_deposit", "pic_deposit_noalloc", "pic_deposit_rho", "pic_gather_fields", "pic_deposit_backward",
            "pic_drift", "pic_push", "pic_deposit_esirkepov",
            "pic_plan_create",
            "pic_plan_destroy", "pic_deposit_batched", "pic_plan_info", "pic_check",
@@ -111,6 +111,7 @@ def lib():
                                     P(ctypes.c_int32)]
     L.pic_bins_report_perf.argtypes = [vp, dbl]
     L.pic_deposit.argtypes = [P(PicGrid), P(PicParticles), vp, vp, vp, vp, i32, u32, vp]
+    L.pic_deposit_noalloc.argtypes = [P(PicGrid), P(PicParticles), vp, vp, vp, vp, i32, u32, vp]
     L.pic_deposit_backward.argtypes = [P(PicGrid), P(PicParticles), vp, vp, vp, vp, vp, vp, vp,
                                        vp, vp, vp, vp, u32, vp]
     L.pic_drift.argtypes = [P(PicGrid), P(PicParticles), dbl, vp]
@@ -311,6 +312,22 @@ def deposit(grid, parts, bins, path=PATH_AUTO, flags=0, J=None):
     pc = parts.c()
     _check(lib().pic_deposit(ctypes.byref(grid.c), ctypes.byref(pc), bins.h if bins else None,
                              _ptr(J[0]), _ptr(J[1]), _ptr(J[2]), path, flags, _stream()))
+    return J
+
+
+def deposit_noalloc(grid, parts, bins, path=PATH_AUTO, flags=0, J=None):
+    """pic_deposit_noalloc: as deposit(), with the tile windows in the library's fixed
+    device array (no allocation by the library)."""
+    if isinstance(path, str):
+        path = PATH_NAMES[path]
+    if J is None:
+        J = new_J(grid)
+    if flags & F_DRIFT:
+        parts.generation += 1
+    pc = parts.c()
+    _check(lib().pic_deposit_noalloc(ctypes.byref(grid.c), ctypes.byref(pc),
+                                     bins.h if bins else None, _ptr(J[0]), _ptr(J[1]),
+                                     _ptr(J[2]), path, flags, _stream()))
     return J
 
 
