@@ -30,6 +30,7 @@ _T0 = time.perf_counter()
 def log(msg):
     """Progress line on stderr (the JSON result is the only line on stdout)."""
     print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+TUNE_CACHE = os.path.join(ROOT, "paper_2601_08277_amd", "tune_cache.json")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "deposit_cell_valu_c2_128cubed_o3_hbm_counters.md")
 
 
@@ -94,6 +95,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if os.path.exists(TUNE_CACHE):
+        pic.tuning_load(TUNE_CACHE)     # PIC_PATH_AUTO's density rule
     if args.workload != "c2":
         out = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args, torch, pic, synth)
         print(json.dumps(out), flush=True)
@@ -173,7 +176,8 @@ def main():
         "config": {"workload": f"uniform plasma {args.n}^3 cells, {args.ppc} per cell, order 3, "
                                f"periodic, u~N(0,0.05), dt 0.2; step = deposit (fused drift + "
                                f"mover detection) + rebin under the re-sort policy",
-                   "particles": int(N), "cells": ncell, "path": args.path, "tile": list(tile),
+                   "particles": int(N), "cells": ncell, "path": args.path,
+                   "auto_path": pic.auto_path(grid, bins), "tile": list(tile),
                    "slack": slack},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,

@@ -59,7 +59,8 @@ enum { PIC_BC_PERIODIC = 0, PIC_BC_GUARD = 1 };
 /* Deposition paths. All accumulate in float32; the split-MFMA paths feed the matrix
  * cores hi/lo pairs of bf16 or fp16 operands (three products per pair). */
 enum {
-  PIC_PATH_AUTO = 0,         /* pick per order/density (autotuned plan or built-in rule) */
+  PIC_PATH_AUTO = 0,         /* pick per order and density: pic_tuning_load's cache, else */
+                             /* the per-cell VALU path                                    */
   PIC_PATH_ATOMIC = 1,       /* one particle per lane, LDS-atomic tile accumulation        */
   PIC_PATH_CELL_VALU = 2,    /* per-cell register accumulation (rhocell on VALU)           */
   PIC_PATH_MFMA_BF16 = 3,    /* per-row outer-product contraction on MFMA, split bf16     */
@@ -337,8 +338,10 @@ pic_status pic_plan_destroy(pic_plan* plan);
  * pointers) into J3[3k], J3[3k+1], J3[3k+2] (host array of 3 npatch device pointers), with
  * the flags of pic_deposit (overwrite unless PIC_F_ACCUMULATE; PIC_F_DRIFT uses grids[k].dt;
  * PIC_F_EMIT_MOVERS fills each patch's mover list for pic_rebin). path: PIC_PATH_AUTO or
- * PIC_PATH_CELL_VALU (else UNSUPPORTED). Enqueues three kernels on `stream` and nothing
- * else once the pointer set has been uploaded: the first call with new pointers copies the
+ * PIC_PATH_CELL_VALU (else UNSUPPORTED); under AUTO, patches the plan put on a matrix path
+ * (pic_plan_patch_path) run as their own launches after the persistent one, except with
+ * PIC_F_MIDPOINT, which only the per-cell path has. Enqueues three kernels on `stream`
+ * (plus two per matrix-path patch) and nothing else once the pointer set has been uploaded: the first call with new pointers copies the
  * patch descriptors from pinned memory (and waits for the previous copy of that buffer),
  * which is refused (INVALID_ARG) while `stream` is capturing. Calls with unchanged pointers
  * allocate nothing, do not synchronise and contain no memset: safe to capture into a HIP
@@ -349,6 +352,23 @@ pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* particles,
  * plan (any pointer may be NULL). */
 pic_status pic_plan_info(const pic_plan* plan, int* nitems, int* blocks, int* blocks_per_cu,
                          int64_t* lds_bytes);
+
+/* Path choice of PIC_PATH_AUTO by density (the paper runs its matrix kernel in dense
+ * regions and vector kernels in sparse ones: Sec. 6.1, Sec. 7). pic_tuning_load reads the
+ * autotuner's JSON cache (host path; NULL clears it): each entry {"order": o, "ppc": p,
+ * "path": "cell_valu" | "mfma_fp16" | "mfma_bf16" | "atomic", ...} names the fastest path
+ * measured for shape order o at p particles per cell. AUTO then takes, for the grid's
+ * order, the entry whose ppc is nearest (log scale) to the bins' particles per cell (the
+ * count of the newest rebin statistics the host has read, else nslots / ((1 + slack)
+ * nbins)); with no entry for the order, or no cache, the per-cell VALU path. The table is
+ * process-wide. Errors: INVALID_ARG (unreadable file, malformed entry, unknown path). */
+pic_status pic_tuning_load(const char* json_path);
+/* The path PIC_PATH_AUTO would take now for these bins (PIC_PATH_CELL_VALU on bad input). */
+int pic_auto_path(const pic_grid* grid, const pic_bins* bins);
+/* The path a batched plan runs patch `patch` on under PIC_PATH_AUTO, fixed by the tuning
+ * table when the plan was created (PIC_PATH_CELL_VALU or a matrix path; matrix-path patches
+ * are launched on their own after the persistent kernel). */
+pic_status pic_plan_patch_path(const pic_plan* plan, int patch, int* path);
 
 /* Synchronises `stream` and reports the first device-side error recorded in `bins`
  * (PIC_OK if none); clears the flags. */

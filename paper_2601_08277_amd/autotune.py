@@ -1,18 +1,24 @@
-"""Tile-shape and launch-shape autotuner for the per-cell deposition path.
+"""Tile-shape, path and launch-shape autotuner for the deposition.
 
-The paper fixes one tile size per run (Appendix A); patches of different shape order and
-density want different tiles on gfx950 (the LDS window grows with the tile and the order,
-and occupancy follows the LDS). For each (order, particles-per-cell bucket) the tuner
-times candidate tiles on a synthetic patch of that class and keeps the fastest; it also
-times the persistent batched launch at each feasible number of workgroups per compute
-unit. The result is a JSON cache:
+The paper fixes one tile size per run (Appendix A) and runs its matrix kernel where cells
+are dense, vector kernels where they are sparse (Sec. 6.1, Sec. 7). On gfx950 both choices
+are measured: for each (shape order, particles-per-cell bucket) the tuner times every
+candidate tile on a synthetic guard-bounded patch of that class with each deposition path
+(per-cell VALU, split-fp16 and split-bf16 MFMA, LDS-atomic), and keeps the fastest (tile,
+path) among the paths that meet the float32 tolerance (the split-bf16 path, at about 4e-6,
+does not and is only reported). It also times the persistent batched launch at each
+feasible number of workgroups per compute unit. The result is a JSON cache:
 
     {"device": "...", "entries": [{"order": 3, "ppc": 8, "tile": [8, 8, 4],
-                                   "path": "cell_valu", "ms": 0.41}, ...],
+                                   "path": "cell_valu", "ms": 0.41,
+                                   "ms_paths": {"cell_valu": 0.41, "mfma_fp16": 2.3, ...}},
+                                  ...],
      "blocks_per_cu": 3}
 
-`lookup` picks the entry of the nearest ppc bucket for an order; `pic_plan_create` reads
-"blocks_per_cu". Timing uses HIP events on the current stream.
+`lookup` picks the entry of the nearest ppc bucket for an order (tiles for the bins);
+`pic_tuning_load` hands the same file to the library, whose PIC_PATH_AUTO then follows
+the entries' paths by density; `pic_plan_create` reads "blocks_per_cu". Timing uses HIP
+events on the current stream.
 """
 import json
 import math
@@ -20,7 +26,9 @@ import math
 import numpy as np
 
 DEFAULT_TILES = [(8, 8, 4), (8, 8, 8), (4, 8, 8), (8, 4, 4), (4, 4, 4), (16, 8, 4), (8, 16, 4)]
-DEFAULT_PPC = (2, 8, 32)
+DEFAULT_PPC = (2, 8, 32, 64)
+PATHS = ("cell_valu", "mfma_fp16", "mfma_bf16", "atomic")
+AUTO_PATHS = ("cell_valu", "mfma_fp16", "atomic")   # within the float32 tolerance
 
 
 def _time(fn, reps):
@@ -38,8 +46,9 @@ def _time(fn, reps):
 
 
 def tune_tiles(orders=(1, 2, 3), ppcs=DEFAULT_PPC, tiles=DEFAULT_TILES, n=(48, 48, 48),
-               reps=5, seed=0, log=None):
-    """Fastest tile per (order, ppc) on a guard-bounded n-cell patch."""
+               reps=5, seed=0, paths=PATHS, log=None):
+    """Fastest (tile, path) per (order, ppc) on a guard-bounded n-cell patch; every path's
+    best time is kept in "ms_paths"."""
     from . import pic, synth
     entries = []
     for order in orders:
@@ -51,23 +60,29 @@ def tune_tiles(orders=(1, 2, 3), ppcs=DEFAULT_PPC, tiles=DEFAULT_TILES, n=(48, 4
             slots = pic.slots_for(N, int(np.prod(n)), 0.25)
             parts = pic.Particles.from_arrays(arrays, slots)
             J = pic.new_J(grid)
-            best = None
+            best = {}          # path -> (ms, tile)
             for tile in tiles:
                 try:
                     bins = pic.Bins(grid, tile, 0.25, slots)
                     pic.rebin(grid, parts, bins, pic.REBIN_FULL)
-                    ms = _time(lambda: pic.deposit(grid, parts, bins, "cell_valu",
-                                                   pic.F_ACCUMULATE, J=J), reps)
-                    bins.close()
                 except pic.PicError:
                     continue
-                if log:
-                    log(f"order {order} ppc {ppc} tile {tile}: {ms:.3f} ms")
-                if best is None or ms < best[1]:
-                    best = (tile, ms)
-            if best is not None:
-                entries.append({"order": order, "ppc": ppc, "tile": list(best[0]),
-                                "path": "cell_valu", "ms": best[1]})
+                for path in paths:
+                    try:
+                        ms = _time(lambda: pic.deposit(grid, parts, bins, path, 0, J=J), reps)
+                    except pic.PicError:
+                        continue
+                    if log:
+                        log(f"order {order} ppc {ppc} tile {tile} {path}: {ms:.3f} ms")
+                    if path not in best or ms < best[path][0]:
+                        best[path] = (ms, tile)
+                bins.close()
+            elig = [p for p in AUTO_PATHS if p in best]
+            if elig:
+                win = min(elig, key=lambda p: best[p][0])
+                entries.append({"order": order, "ppc": ppc, "tile": list(best[win][1]),
+                                "path": win, "ms": best[win][0],
+                                "ms_paths": {p: best[p][0] for p in best}})
     return entries
 
 

@@ -26,8 +26,11 @@ struct pic_plan {
   std::vector<BatchPatch> last;      // descriptors last uploaded
   bool uploaded = false;
   hipEvent_t upload_ev = nullptr;
-  int2* d_items = nullptr;
+  int2* d_items = nullptr;           // every patch's tiles
   int nitems = 0;
+  int2* d_items_vec = nullptr;       // tiles of the patches AUTO runs on the per-cell path
+  int nitems_vec = 0;
+  std::vector<int> patch_path;       // PIC_PATH_AUTO's choice per patch (at plan creation)
   int* d_queue = nullptr;
   size_t smem = 0;
   size_t halo_smem = 0;
@@ -59,6 +62,7 @@ static void plan_free(pic_plan* p) {
   if (p->d_pd) (void)hipFree(p->d_pd);
   if (p->h_pd) (void)hipHostFree(p->h_pd);
   if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_items_vec) (void)hipFree(p->d_items_vec);
   if (p->d_queue) (void)hipFree(p->d_queue);
   if (p->upload_ev) (void)hipEventDestroy(p->upload_ev);
   delete p;
@@ -104,19 +108,29 @@ extern "C" pic_status pic_plan_create(const pic_grid* grids, int npatch, pic_bin
     const double per_tile = (double)bins[k]->nslots / (double)kb.ntiles;
     const double o1 = grids[k].order + 1.0;
     for (int t = 0; t < kb.ntiles; ++t) items.push_back({k, t, per_tile * (o1 * o1 * (o1 + 1.0))});
+    const int ch = choose_path(G, bins[k]);
+    p->patch_path.push_back(ch == PIC_PATH_MFMA_BF16 || ch == PIC_PATH_MFMA_FP16 ? ch
+                                                                             : PIC_PATH_CELL_VALU);
   }
   (void)max_lds;
   std::stable_sort(items.begin(), items.end(),
                    [](const Item& a, const Item& b) { return a.cost > b.cost; });
   p->nitems = (int)items.size();
-  std::vector<int2> h_items(items.size());
-  for (size_t i = 0; i < items.size(); ++i) h_items[i] = make_int2(items[i].patch, items[i].tile);
+  std::vector<int2> h_items(items.size()), h_vec;
+  for (size_t i = 0; i < items.size(); ++i) {
+    h_items[i] = make_int2(items[i].patch, items[i].tile);
+    if (p->patch_path[items[i].patch] == PIC_PATH_CELL_VALU) h_vec.push_back(h_items[i]);
+  }
+  p->nitems_vec = (int)h_vec.size();
   int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   if (e == hipSuccess) e = hipMalloc(&p->d_pd, sizeof(BatchPatch) * npatch);
   if (e == hipSuccess) e = hipHostMalloc(&p->h_pd, sizeof(BatchPatch) * npatch, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(&p->d_items, sizeof(int2) * h_items.size());
+  if (e == hipSuccess) e = hipMalloc(&p->d_items_vec, sizeof(int2) * std::max<size_t>(h_vec.size(), 1));
+  if (e == hipSuccess && !h_vec.empty())
+    e = hipMemcpy(p->d_items_vec, h_vec.data(), sizeof(int2) * h_vec.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_queue, sizeof(int) * 4);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->upload_ev, hipEventDisableTiming);
   if (e == hipSuccess)
@@ -143,7 +157,7 @@ extern "C" pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* p
                                           hipStream_t stream) {
   if (!plan || !particles || !J3) return set_error(PIC_ERR_INVALID_ARG, "NULL argument");
   if (path != PIC_PATH_AUTO && path != PIC_PATH_CELL_VALU)
-    return set_error(PIC_ERR_UNSUPPORTED, "batched launches run the per-cell VALU path");
+    return set_error(PIC_ERR_UNSUPPORTED, "batched launches take PIC_PATH_AUTO or PIC_PATH_CELL_VALU");
   if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC | PIC_F_EMIT_MOVERS | PIC_F_DRIFT |
                           PIC_F_MIDPOINT))
     return set_error(PIC_ERR_INVALID_ARG, "unknown flag bits");
@@ -188,15 +202,40 @@ extern "C" pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* p
     plan->last = pd;
     plan->uploaded = true;
   }
+  // AUTO follows the plan's per-patch choice (the matrix paths have no midpoint deposition:
+  // with PIC_F_MIDPOINT every patch runs on the per-cell path)
+  const bool split = path == PIC_PATH_AUTO && !(flags & PIC_F_MIDPOINT) &&
+                     plan->nitems_vec < plan->nitems;
+  const int2* items = split ? plan->d_items_vec : plan->d_items;
+  const int nitems = split ? plan->nitems_vec : plan->nitems;
   batched_prologue_launch(plan->d_pd, plan->npatch, plan->max_nodes, plan->d_queue, flags, stream);
-  batched_cell_launch(plan->d_pd, plan->d_items, plan->nitems, plan->d_queue, plan->blocks,
-                      plan->smem, flags, stream);
-  batched_halo_tile_launch(plan->d_pd, plan->d_items, plan->nitems, plan->halo_smem, stream);
+  if (nitems > 0) {
+    batched_cell_launch(plan->d_pd, items, nitems, plan->d_queue, plan->blocks, plan->smem, flags,
+                        stream);
+    batched_halo_tile_launch(plan->d_pd, items, nitems, plan->halo_smem, stream);
+  }
+  if (split) {
+    // patches on a matrix path: their own launches, J already cleared by the prologue
+    for (int k = 0; k < plan->npatch; ++k) {
+      if (plan->patch_path[k] == PIC_PATH_CELL_VALU) continue;
+      if (!deposit_launch(pd[k].G, pd[k].P, plan->bins[k], J3[3 * k], J3[3 * k + 1],
+                          J3[3 * k + 2], plan->patch_path[k], flags | PIC_F_ACCUMULATE,
+                          plan->grids[k].dt, stream))
+        return set_error(PIC_ERR_UNSUPPORTED, "matrix path not available for a patch");
+    }
+  }
   for (int k = 0; k < plan->npatch; ++k) {
     if (flags & PIC_F_EMIT_MOVERS) plan->bins[k]->movers_fresh = true;
     else if (flags & PIC_F_DRIFT) plan->bins[k]->movers_fresh = false;
   }
   return check_hip(hipGetLastError(), "pic_deposit_batched launch");
+}
+
+extern "C" pic_status pic_plan_patch_path(const pic_plan* plan, int patch, int* path) {
+  if (!plan || !path) return set_error(PIC_ERR_INVALID_ARG, "NULL argument");
+  if (patch < 0 || patch >= plan->npatch) return set_error(PIC_ERR_INVALID_ARG, "no such patch");
+  *path = plan->patch_path[patch];
+  return PIC_OK;
 }
 
 extern "C" pic_status pic_plan_info(const pic_plan* plan, int* nitems, int* blocks,

@@ -2,11 +2,12 @@
 // registers.
 //
 // A workgroup owns one particle tile and walks it in groups of 64 consecutive cells (one
-// z-plane of an 8 x 8 x T tile). Bins are contiguous, so a group's particles are one
-// contiguous slot range; a unit is up to CV_CAP particles of one group. Four waves:
+// z-plane of an 8 x 8 x T tile). A unit takes up to k particles of every cell of a group
+// (at most 512 in all; a group that fits is one unit, a dense one is cut across its cells),
+// so every cell lane has work at any density. Four waves:
 //  producer   (wave 3) stages unit u + 1 while the consumers work on unit u. Lanes = the
-//             unit's particles (each one's cell found by a binary search over the group's
-//             staged ranges, so gap slots take no lane), coalesced loads: position -> cell
+//             unit's particles (each one's cell read from the unit's table, built by the
+//             cell lanes, so gap slots take no lane), coalesced loads: position -> cell
 //             + float32 offset (FP64 only here) and amplitude q W v_c. Offsets and
 //             amplitudes go to a double-buffered LDS stage in cell order. A particle whose
 //             cell no longer matches its bin goes to a stale list.
@@ -58,7 +59,9 @@ constexpr int CV_GROUP = 64;    // cells per group (lanes)
 constexpr int CV_CAP = 512;     // staged particles per unit (gap slots skipped)
 // Per-unit table (bytes): the cell (group lane) of each staged particle, int8[CV_CAP], with
 // CV_TAB_BAD set when the producer found its position outside the domain or not finite,
-// then each cell's staged start, int32[CV_GROUP]; double-buffered like the stage.
+// then each cell's staged start minus its particles staged by earlier units of the group,
+// int32[CV_GROUP] (staged index + that = index inside the cell's bin); double-buffered like
+// the stage.
 constexpr int CV_TAB = CV_CAP + 4 * CV_GROUP;
 constexpr int CV_TAB_BAD = 64;   // table flag: the particle's staged position is not valid
 constexpr int CV_CONS = 3;      // consumer waves, one per current component
@@ -99,54 +102,85 @@ struct CellLayout {
   }
 };
 
-// A unit of work: up to CV_CAP particles of one group of 64 consecutive cells. Every
-// wave walks the same sequence of units (empty groups skipped).
+// A unit of work: up to k particles of every cell of one group of 64 consecutive cells, the
+// next ones of each cell (in slot order) after those of the group's earlier units, with k
+// the largest count that keeps the unit within CV_CAP particles. A group that fits takes one
+// unit; a dense group is cut across its cells (k >= CV_CAP / 64), so the 64 consumer lanes
+// (one per cell) all have particles whatever the density. Every wave walks the same
+// sequence of units (empty groups skipped).
 struct CellGroup {
   int g0, gn;        // first tile-local bin, cells
-  int S0, S1;        // slot range
-  int n, st;         // this lane's cell: particles (valid slots), staged offset
-  int ntot;          // particles of the group
-  int R0;            // staged index of the unit's first particle
+  int n;             // this lane's cell: particles (valid slots)
+  int done;          // this lane's cell: particles staged by the group's earlier units
+  int m, ust;        // this lane's cell in this unit: particles, staged start
+  int nunit;         // particles of this unit
+  bool last;         // no particles of the group are left after this unit
 };
 
-// The group starting at tile-local bin g0 (g0 >= nb: past the end, no particles). Every
-// field is written once, so the struct stays in registers.
-__device__ __forceinline__ CellGroup cv_group_at(int g0, const int32_t* s_off,
-                                                 const int32_t* s_len, int nb, int lane) {
-  const bool valid = g0 < nb;
-  const int gs = valid ? g0 : 0;
-  const int gn = valid ? min(CV_GROUP, nb - g0) : 0;
-  const int n = lane < gn ? s_len[gs + lane] : 0;
-  int incl = n;
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Per-lane count and staged start of the next unit of the group (wave reductions and a scan
+// over the group's cells).
+__device__ __forceinline__ void cv_unit_fields(CellGroup& gr, int lane) {
+  const int r = gr.n - gr.done;
+  const int rtot = wave_sum(r);
+  int k = wave_max(r);
+  if (rtot > CV_CAP) {
+    // largest k with sum_c min(r_c, k) <= CV_CAP (k = 1 always fits: 64 <= CV_CAP)
+    int lo = 1, hi = k;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (wave_sum(min(r, mid)) <= CV_CAP) lo = mid;
+      else hi = mid - 1;
+    }
+    k = lo;
+  }
+  const int m = min(r, k);
+  int incl = m;
 #pragma unroll
   for (int off = 1; off < PIC_WAVE; off <<= 1) {
     const int t = __shfl_up(incl, off);
     if (lane >= off) incl += t;
   }
+  gr.m = m;
+  gr.ust = incl - m;
+  gr.nunit = __shfl(incl, PIC_WAVE - 1);
+  gr.last = gr.nunit == rtot;
+}
+
+// The group starting at tile-local bin g0 (g0 >= nb: past the end, no particles), at its
+// first unit. Every field is written once per unit, so the struct stays in registers.
+__device__ __forceinline__ CellGroup cv_group_at(int g0, const int32_t* s_off,
+                                                 const int32_t* s_len, int nb, int lane) {
+  const bool valid = g0 < nb;
+  const int gs = valid ? g0 : 0;
+  const int gn = valid ? min(CV_GROUP, nb - g0) : 0;
   CellGroup gr;
   gr.g0 = g0;
   gr.gn = gn;
-  gr.S0 = valid ? s_off[gs] : 0;
-  gr.S1 = valid ? s_off[gs + gn] : 0;
-  gr.n = n;
-  gr.st = incl - n;
-  gr.ntot = __shfl(incl, PIC_WAVE - 1);
-  gr.R0 = 0;
+  gr.n = lane < gn ? s_len[gs + lane] : 0;
+  gr.done = 0;
+  cv_unit_fields(gr, lane);
   return gr;
 }
 
 __device__ __forceinline__ CellGroup cv_first_unit(int g0, const int32_t* s_off,
                                                    const int32_t* s_len, int nb, int lane) {
   CellGroup gr = cv_group_at(g0, s_off, s_len, nb, lane);
-  while (gr.g0 < nb && gr.ntot == 0) gr = cv_group_at(gr.g0 + CV_GROUP, s_off, s_len, nb, lane);
+  while (gr.g0 < nb && gr.nunit == 0) gr = cv_group_at(gr.g0 + CV_GROUP, s_off, s_len, nb, lane);
   return gr;
 }
 
 __device__ __forceinline__ CellGroup cv_next_unit(const CellGroup& cur, const int32_t* s_off,
                                                   const int32_t* s_len, int nb, int lane) {
-  if (cur.R0 + CV_CAP < cur.ntot) {
+  if (!cur.last) {
     CellGroup gr = cur;
-    gr.R0 = cur.R0 + CV_CAP;
+    gr.done = cur.done + cur.m;
+    cv_unit_fields(gr, lane);
     return gr;
   }
   return cv_first_unit(cur.g0 + CV_GROUP, s_off, s_len, nb, lane);
@@ -225,8 +259,8 @@ __device__ __forceinline__ void cv_particle_global(const KGrid& G, PartPrep<O, D
   });
 }
 
-// Producer wave: stage the unit's particles (staged index in [R0, R0 + CV_CAP)) into one
-// stage buffer, lanes = particles, so no lane idles on a gap slot. The unit's table gives
+// Producer wave: stage the unit's particles (cell by cell, staged index in [0, nunit)) into
+// one stage buffer, lanes = particles, so no lane idles on a gap slot. The unit's table gives
 // each staged particle's cell (each cell lane writes its own range [st, st + n) of it) and
 // each cell's staged start; the consumers' drift reads the same table. Coalesced loads;
 // three chunks' loads are in flight ahead of the one being processed (memory latency,
@@ -240,20 +274,17 @@ __device__ __forceinline__ void cv_stage(const KGrid& G, const KBins& B, const K
   const int lane = threadIdx.x % PIC_WAVE;
   const int pw = threadIdx.x / PIC_WAVE - CV_CONS;   // producer index
   const int ex = tb.e[0];
-  const int nunit = min(CV_CAP, gr.ntot - gr.R0);
+  const int nunit = gr.nunit;
   const int first = pw * PIC_WAVE, step = CV_PROD * PIC_WAVE;
   int32_t* tst = (int32_t*)(tab + CV_CAP);
   wave_lds_sync();
-  tst[lane] = gr.st;
-  {
-    const int k0 = max(0, gr.R0 - gr.st), k1 = min(gr.n, gr.R0 + nunit - gr.st);
-    for (int k = k0; k < k1; ++k) tab[gr.st + k - gr.R0] = (int8_t)lane;
-  }
+  tst[lane] = gr.ust - gr.done;
+  for (int k = 0; k < gr.m; ++k) tab[gr.ust + k] = (int8_t)lane;
   wave_lds_sync();
   auto fetch = [&](int base, CvRaw& r) {
     r.si = base + lane;
     r.lc = r.si < nunit ? (int)tab[r.si] : -1;
-    r.s = r.lc >= 0 ? s_off[gr.g0 + r.lc] + (gr.R0 + r.si - tst[r.lc]) : 0;
+    r.s = r.lc >= 0 ? s_off[gr.g0 + r.lc] + (r.si - tst[r.lc]) : 0;
     if (r.lc >= 0) {
       r.x = P.x[r.s];
       r.y = P.y[r.s];
@@ -518,13 +549,13 @@ __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, co
   const bool emit = flags & PIC_F_EMIT_MOVERS;
   const bool drift = flags & PIC_F_DRIFT;
   const int ex = tb.e[0];
-  const int nunit = min(CV_CAP, gr.ntot - gr.R0);
+  const int nunit = gr.nunit;
   for (int base = wave * PIC_WAVE; base < nunit; base += CV_CONS * PIC_WAVE) {
     const int j = base + lane;
     const bool in_unit = j < nunit;
     const int tv = in_unit ? (int)tab[j] : 0;
     const int c = tv & (CV_GROUP - 1);
-    const int s = in_unit ? s_off[gr.g0 + c] + (gr.R0 + j - ((const int32_t*)(tab + CV_CAP))[c]) : 0;
+    const int s = in_unit ? s_off[gr.g0 + c] + (j - ((const int32_t*)(tab + CV_CAP))[c]) : 0;
     const int lb = gr.g0 + (in_unit ? c : 0);
     bool ok = false, mv = false;
     int32_t nbn = -1;
@@ -636,9 +667,8 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
     while (cur.g0 < tb.nb) {
       const CellGroup nxt = cv_next_unit(cur, s_off, s_len, tb.nb, lane);
       const float* sf = stage + ub * 6 * CV_CAP;
-      const int k0 = min(max(cur.st, cur.R0), cur.R0 + CV_CAP) - cur.R0;
-      const int k1 = min(max(cur.st + cur.n, cur.R0), cur.R0 + CV_CAP) - cur.R0;
-      const bool last = cur.R0 + CV_CAP >= cur.ntot;
+      const int k0 = cur.ust, k1 = cur.ust + cur.m;
+      const bool last = cur.last;
       if (wave == 0) cv_consume<O, DIM, 0, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       else if (wave == 1) cv_consume<O, DIM, 1, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       else cv_consume<O, DIM, 2, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
@@ -765,12 +795,6 @@ bool deposit_rho_cell_launch(const KGrid& G, const KPart& P, pic_bins* b, float*
     if (G.order == 1) CR(1, 2); else if (G.order == 2) CR(2, 2); else CR(3, 2);
   }
 #undef CR
-}
-
-int choose_path(const KGrid& G, const pic_bins* b) {
-  (void)G;
-  (void)b;
-  return PIC_PATH_CELL_VALU;
 }
 
 bool deposit_cell_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, float* J1,

@@ -28,8 +28,8 @@ EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "p
            "pic_deposit", "pic_deposit_noalloc", "pic_deposit_rho", "pic_gather_fields", "pic_deposit_backward",
            "pic_drift", "pic_push", "pic_deposit_esirkepov",
            "pic_plan_create",
-           "pic_plan_destroy", "pic_deposit_batched", "pic_plan_info", "pic_check",
-           "pic_last_error"]
+           "pic_plan_destroy", "pic_deposit_batched", "pic_plan_info", "pic_plan_patch_path",
+           "pic_tuning_load", "pic_auto_path", "pic_check", "pic_last_error"]
 
 
 class PicError(RuntimeError):
@@ -121,6 +121,9 @@ def lib():
     L.pic_plan_destroy.argtypes = [vp]
     L.pic_deposit_batched.argtypes = [vp, P(PicParticles), P(vp), i32, u32, vp]
     L.pic_check.argtypes = [vp, vp]
+    L.pic_tuning_load.argtypes = [ctypes.c_char_p]
+    L.pic_auto_path.argtypes = [P(PicGrid), vp]
+    L.pic_plan_patch_path.argtypes = [vp, i32, P(ctypes.c_int)]
     for name in EXPORTS:
         if name not in ("pic_last_error", "pic_sort_policy_default", "pic_policy_decide"):
             getattr(L, name).restype = i32
@@ -272,6 +275,17 @@ class Bins:
         _check(lib().pic_bins_report_perf(self.h, float(perf)))
 
 
+def tuning_load(path):
+    """Load the autotuner's cache as PIC_PATH_AUTO's density rule (None clears it)."""
+    _check(lib().pic_tuning_load(path.encode() if path else None))
+
+
+def auto_path(grid, bins):
+    """The path PIC_PATH_AUTO would take for these bins, as a name."""
+    p = lib().pic_auto_path(ctypes.byref(grid.c), bins.h)
+    return {v: k for k, v in PATH_NAMES.items()}[p]
+
+
 def check_nobins():
     _check(lib().pic_check(None, _stream()))
 
@@ -352,6 +366,11 @@ class Plan:
                                    ctypes.byref(lds)))
         return {"items": ni.value, "blocks": nb.value, "blocks_per_cu": bpc.value,
                 "lds_bytes": lds.value}
+
+    def patch_path(self, k):
+        v = ctypes.c_int()
+        _check(lib().pic_plan_patch_path(self.h, int(k), ctypes.byref(v)))
+        return {v_: k_ for k_, v_ in PATH_NAMES.items()}[v.value]
 
     def close(self):
         if self.h:

@@ -1,6 +1,7 @@
 """CPU checks of the C ABI: the library loads, exports every function pic.h declares, the
 host-side policy agrees with the oracle, and argument errors are reported without a GPU."""
 import ctypes
+import json
 import os
 import re
 
@@ -151,3 +152,30 @@ def test_argument_errors_of_the_next_rows_without_gpu(L):
     assert L.pic_deposit_rho(ctypes.byref(g), ctypes.byref(p), None, f, pic.F_DRIFT, None) == -1
     assert L.pic_gather_fields(ctypes.byref(g), ctypes.byref(p), None, *[f] * 11, None,
                                None) == -1
+
+
+def test_tuning_cache_parser(L, tmp_path):
+    """pic_tuning_load reads the autotuner's cache (nested "tile" lists and "ms_paths"
+    objects included) and rejects malformed or unknown entries; no GPU needed."""
+    from paper_2601_08277_amd import pic
+    committed = os.path.join(ROOT, "paper_2601_08277_amd", "tune_cache.json")
+    assert L.pic_tuning_load(committed.encode()) == pic.PIC_OK
+    good = tmp_path / "good.json"
+    good.write_text(json.dumps({"device": "x", "entries": [
+        {"order": 3, "ppc": 8, "tile": [8, 8, 4], "path": "mfma_fp16", "ms": 1.0,
+         "ms_paths": {"cell_valu": 0.5, "mfma_fp16": 1.0, "path": 3}},
+        {"order": 1, "ppc": 2, "tile": [8, 4, 4], "path": "cell_valu", "ms": 0.1}],
+        "blocks_per_cu": 2}))
+    assert L.pic_tuning_load(str(good).encode()) == pic.PIC_OK
+    for bad in ({"entries": [{"order": 3, "ppc": 8, "path": "fastest"}]},
+                {"entries": [{"order": 4, "ppc": 8, "path": "cell_valu"}]},
+                {"entries": [{"order": 3, "path": "cell_valu"}]},
+                {"no_entries": []}):
+        f = tmp_path / "bad.json"
+        f.write_text(json.dumps(bad))
+        assert L.pic_tuning_load(str(f).encode()) == pic.PIC_ERR_INVALID_ARG, bad
+    f = tmp_path / "trunc.json"
+    f.write_text(json.dumps({"entries": [{"order": 3, "ppc": 8, "path": "cell_valu"}]})[:-3])
+    assert L.pic_tuning_load(str(f).encode()) == pic.PIC_ERR_INVALID_ARG
+    assert L.pic_tuning_load(str(tmp_path / "missing.json").encode()) == pic.PIC_ERR_INVALID_ARG
+    assert L.pic_tuning_load(None) == pic.PIC_OK
