@@ -153,7 +153,7 @@ extern "C" int pic_policy_decide(const pic_sort_policy* p, int steps_since_sort,
 // ----------------------------------------------------------------------------------
 static void free_bins(pic_bins* b) {
   if (!b) return;
-  int32_t* bufs[] = {b->kb.off, b->kb.len, b->kb.moved_out, b->kb.ins_cnt, b->kb.tile_flag,
+  int32_t* bufs[] = {b->kb.off, b->kb.len, b->kb.out_flag, b->kb.ins_cnt, b->kb.tile_flag,
                      b->kb.mv_slot, b->kb.mv_old, b->kb.mv_new, b->bin_cell, b->sbin,
                      b->scratch.id, b->scan_tmp[0], b->scan_tmp[1], b->scan_tmp[2],
                      b->scan_tmp[3]};
@@ -221,7 +221,7 @@ extern "C" pic_status pic_bins_create(const pic_grid* grid, const int tile[3], d
   };
   A(dalloc(&b->kb.off, nbins + 1));
   A(dalloc(&b->kb.len, nbins));
-  A(dalloc(&b->kb.moved_out, nbins));
+  A(dalloc(&b->kb.out_flag, nbins));
   A(dalloc(&b->kb.ins_cnt, nbins));
   A(dalloc(&b->kb.tile_flag, ntiles));
   A(dalloc(&b->kb.mv_slot, max_movers));
@@ -279,7 +279,7 @@ extern "C" pic_status pic_bins_create(const pic_grid* grid, const int tile[3], d
   A(hipMemcpy(b->bin_cell, bc.data(), bc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   A(hipMemset(b->kb.off, 0, (size_t)(nbins + 1) * sizeof(int32_t)));
   A(hipMemset(b->kb.len, 0, (size_t)nbins * sizeof(int32_t)));
-  A(hipMemset(b->kb.moved_out, 0, (size_t)nbins * sizeof(int32_t)));
+  A(hipMemset(b->kb.out_flag, 0, (size_t)nbins * sizeof(int32_t)));
   A(hipMemset(b->kb.ins_cnt, 0, (size_t)nbins * sizeof(int32_t)));
   A(hipMemset(b->kb.tile_flag, 0, (size_t)ntiles * sizeof(int32_t)));
   A(hipMemset(b->dctr, 0, sizeof(CtrBlock)));

@@ -59,7 +59,7 @@ struct KBins {
   int32_t nbins, ntiles;
   int32_t* off;       // nbins + 1
   int32_t* len;       // nbins
-  int32_t* moved_out; // nbins
+  int32_t* out_flag;  // nbins: 1 if a particle left the bin in this rebin (compaction pending)
   int32_t* ins_cnt;   // nbins
   int32_t* tile_flag; // ntiles
   int32_t* mv_slot;   // max_movers

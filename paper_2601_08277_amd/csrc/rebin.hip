@@ -125,13 +125,9 @@ __device__ __forceinline__ void copy_slot(const KPart& D, int d, const KPart& S,
   store_slot(D, d, p);
 }
 
+// A gap slot is marked by its id and weight alone (every kernel tests the id before it
+// reads a slot's payload), so turning a slot into a gap touches two arrays, not eight.
 __device__ __forceinline__ void set_gap(const KPart& D, int d) {
-  D.x[d] = 0.0;
-  D.y[d] = 0.0;
-  D.z[d] = 0.0;
-  D.ux[d] = 0.0f;
-  D.uy[d] = 0.0f;
-  D.uz[d] = 0.0f;
   D.w[d] = 0.0f;
   D.id[d] = PIC_INVALID_ID;
 }
@@ -296,7 +292,7 @@ __global__ __launch_bounds__(256) void k_full_rank(KBins B, KPart S, int32_t* __
     }
     for (int j = n; j < cap; ++j) src[o + j] = -1;
     B.ins_cnt[b] = 0;
-    B.moved_out[b] = 0;
+    B.out_flag[b] = 0;
   }
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   for (int t = tid; t < B.ntiles; t += stride) B.tile_flag[t] = 0;
@@ -409,9 +405,8 @@ __global__ __launch_bounds__(256) void k_insert(KBins B, KPart P, const int32_t*
     const bool fits = pos < cap;
     if (fits) {
       store_slot(P, B.off[nb] + pos, pl);
-      P.id[s] = PIC_INVALID_ID;
-      P.w[s] = 0.0f;
-      atomicAdd(&B.moved_out[ob], 1);
+      set_gap(P, s);
+      B.out_flag[ob] = 1;     // the source bin has a hole (plain store: every writer writes 1)
     } else {
       int c = bin_cell[nb];
       int i = c % nx, j = (c / nx) % ny, kk = c / (nx * ny);
@@ -425,31 +420,36 @@ __global__ __launch_bounds__(256) void k_insert(KBins B, KPart P, const int32_t*
   }
 }
 
+// Compaction of every bin that lost or gained particles: holes (gap slots) in the old dense
+// prefix [0, L) are filled, in slot order, by the valid entries at or above the new length
+// (the prefix's tail, then the inserted particles ordered by id): swap-with-last of the
+// paper's delete, with one payload copy per hole. The bin's hole count is read from the
+// ids themselves.
 __global__ __launch_bounds__(256) void k_compact(KBins B, KPart P) {
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < B.nbins; b += gridDim.x * blockDim.x) {
-    const int out = B.moved_out[b], ins = B.ins_cnt[b];
-    if (out == 0 && ins == 0) continue;
+    const int outf = B.out_flag[b], ins = B.ins_cnt[b];
+    if (outf == 0 && ins == 0) continue;
     const int o = B.off[b];
     const int L = B.len[b];
     const int cap = B.off[b + 1] - o;
     const int I = min(ins, cap - L);
     if (I >= 2) sort_range_by_id(P, o + L, I);
     const int total = L + I;
-    const int nl = total - out;
-    // swap-with-last: holes below nl take the valid entries at or above nl, in order
     if (total <= 16) {
       // ids read at once (independent loads), holes and sources as bit masks
       int32_t ids[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) ids[k] = k < total ? P.id[o + k] : 0;
-      unsigned holes = 0u, srcs = 0u, tail_gaps = 0u;
+      for (int k = 0; k < 16; ++k) ids[k] = k < L ? P.id[o + k] : 0;
+      unsigned gaps = 0u;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const bool gap = k < total && ids[k] == PIC_INVALID_ID;
-        if (k < nl && gap) holes |= 1u << k;
-        if (k >= nl && k < total && !gap) srcs |= 1u << k;
-        if (k >= nl && gap) tail_gaps |= 1u << k;
-      }
+      for (int k = 0; k < 16; ++k)
+        if (k < L && ids[k] == PIC_INVALID_ID) gaps |= 1u << k;
+      const int nl = total - __builtin_popcount(gaps);
+      // holes below nl; sources: valid entries at or above nl (inserted ones are valid)
+      const unsigned below = nl >= 32 ? ~0u : ((1u << nl) - 1u);
+      const unsigned all = total >= 32 ? ~0u : ((1u << total) - 1u);
+      unsigned holes = gaps & below;
+      unsigned srcs = all & ~below & ~gaps;
       while (holes && srcs) {
         const int h = __builtin_ctz(holes), t = __builtin_ctz(srcs);
         copy_slot(P, o + h, P, o + t);
@@ -457,11 +457,11 @@ __global__ __launch_bounds__(256) void k_compact(KBins B, KPart P) {
         holes &= holes - 1u;
         srcs &= srcs - 1u;
       }
-      while (tail_gaps) {
-        set_gap(P, o + __builtin_ctz(tail_gaps));
-        tail_gaps &= tail_gaps - 1u;
-      }
+      B.len[b] = nl;
     } else {
+      int out = 0;
+      for (int i = 0; i < L; ++i) out += P.id[o + i] == PIC_INVALID_ID ? 1 : 0;
+      const int nl = total - out;
       int top = nl;
       for (int i = 0; i < nl; ++i) {
         if (P.id[o + i] != PIC_INVALID_ID) continue;
@@ -471,11 +471,9 @@ __global__ __launch_bounds__(256) void k_compact(KBins B, KPart P) {
         set_gap(P, o + top);
         ++top;
       }
-      for (int i = nl; i < total; ++i)
-        if (P.id[o + i] == PIC_INVALID_ID) set_gap(P, o + i);
+      B.len[b] = nl;
     }
-    B.len[b] = nl;
-    B.moved_out[b] = 0;
+    B.out_flag[b] = 0;
     B.ins_cnt[b] = 0;
   }
 }
