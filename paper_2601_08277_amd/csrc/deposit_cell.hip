@@ -15,10 +15,10 @@
 //             staged particles and accumulates (amp_c s_x) (x) s_y (x) s_z of component c
 //             on the cell's padded stencil window in registers (Eq. 4); after the group's
 //             last unit it adds them to the tile window in LDS (Eq. 5) with plain
-//             read-add-write. After each unit the three waves share the fused drift and
-//             mover detection (stage 1 of Alg. 2) of its slots, movers going to LDS
-//             buffers. The consumers write different components, so they never
-//             share a word. LDS float atomics cost about 190 cycles per wave instruction
+//             read-add-write. After each unit they and the producer (after staging the
+//             next unit) share the fused drift and mover detection (stage 1 of Alg. 2) of
+//             its particles, a quarter each, movers going to per-wave LDS buffers. The
+//             consumers write different components, so they never share a word. LDS float atomics cost about 190 cycles per wave instruction
 //             on gfx950 (integer ones about 5) and are not used.
 //  end        the consumers add the stale particles (one at a time, lanes = stencil nodes)
 //             and the tile window goes to the window scratch; k_halo_tile adds neighbouring
@@ -87,7 +87,7 @@ struct StaleRec {
 };
 
 // LDS layout of one workgroup (bytes): bin offsets and lengths | tile window (3 comps)
-// | two stage buffers f[3][CAP], a[3][CAP] | two unit tables | per consumer: mover buffer
+// | two stage buffers f[3][CAP], a[3][CAP] | two unit tables | per wave: mover buffer
 // | stale list and its count.
 template <int O, int DIM>
 struct CellLayout {
@@ -97,7 +97,7 @@ struct CellLayout {
     stage_off = win_off + (((size_t)3 * TileWin<O, DIM>::max_size(kb) * sizeof(float) + 15) & ~(size_t)15);
     tab_off = stage_off + (size_t)2 * 6 * CV_CAP * sizeof(float);
     mb_off = tab_off + (size_t)2 * CV_TAB;
-    stale_off = mb_off + (size_t)CV_CONS * 3 * MBUF * sizeof(int32_t);
+    stale_off = mb_off + (size_t)CV_WAVES * 3 * MBUF * sizeof(int32_t);
     total = stale_off + (size_t)CV_STALE * sizeof(StaleRec) + 16;
   }
 };
@@ -534,10 +534,11 @@ __device__ __forceinline__ void cv_flush_group(const TileBox& tb, const TileWin<
   else cv_flush<O, DIM, C, false, RHO>(tw, cc, acc, win, o);
 }
 
-// Consumer wave c, after accumulating a unit: the fused drift (x += v dt, FP64) and mover
-// detection (stage 1 of Alg. 2) for every third chunk of 64 of the unit's particles, lanes
-// = particles (each one's cell and slot from the unit's table, so gap slots take no lane).
-// It is done here rather than in the producer, whose loads bound the unit pipeline.
+// Fused drift (x += v dt, FP64) and mover detection (stage 1 of Alg. 2) of a unit, lanes =
+// particles (each one's cell and slot from the unit's table, so gap slots take no lane):
+// wave w takes chunk j of 64 when j mod 4 = w. The three accumulating waves do theirs after
+// accumulating the unit, the producer after staging the next unit: the accumulation keeps
+// the consumers' SIMDs busier than the producer's, so the producer takes an equal share.
 template <int DIM>
 __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, const KPart& P,
                                               const TileBox& tb, const int32_t* s_off,
@@ -550,7 +551,7 @@ __device__ __forceinline__ void cv_drift_unit(const KGrid& G, const KBins& B, co
   const bool drift = flags & PIC_F_DRIFT;
   const int ex = tb.e[0];
   const int nunit = gr.nunit;
-  for (int base = wave * PIC_WAVE; base < nunit; base += CV_CONS * PIC_WAVE) {
+  for (int base = wave * PIC_WAVE; base < nunit; base += CV_WAVES * PIC_WAVE) {
     const int j = base + lane;
     const bool in_unit = j < nunit;
     const int tv = in_unit ? (int)tab[j] : 0;
@@ -624,7 +625,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   const int wave = threadIdx.x / PIC_WAVE;
   const int lane = threadIdx.x % PIC_WAVE;
   const bool producer = wave >= CV_CONS;
-  int32_t* mbb = (int32_t*)(smem_raw + L.mb_off) + (producer ? 0 : wave) * 3 * MBUF;
+  int32_t* mbb = (int32_t*)(smem_raw + L.mb_off) + wave * 3 * MBUF;
   StaleRec* stale = (StaleRec*)(smem_raw + L.stale_off);
   int* s_nstale = (int*)(smem_raw + L.stale_off + CV_STALE * sizeof(StaleRec));
   float* J[3] = {J0, J1, J2};
@@ -641,6 +642,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
   // The producer and the consumers run separate loops over the same units with one
   // barrier per unit (plus one after the first unit is staged), so the consumers'
   // accumulators are not live across the producer's code.
+  const bool drift = !RHO && (flags & (PIC_F_DRIFT | PIC_F_EMIT_MOVERS));
   if (producer) {
     if (cur.g0 < tb.nb)
       cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, cur, stage, stage + 3 * CV_CAP, tab,
@@ -654,10 +656,14 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
         cv_stage<O, DIM, RHO>(G, B, P, tb, s_off, s_len, nxt, nf, nf + 3 * CV_CAP,
                               tab + (ub ^ 1) * CV_TAB, stale, s_nstale, J, bad, hdt);
       }
+      if (drift)
+        cv_drift_unit<DIM>(G, B, P, tb, s_off, s_len, cur, tab + ub * CV_TAB, hdt == 0.0f, wave,
+                           mb, flags, dt, bad);
       __syncthreads();
       cur = nxt;
       ub ^= 1;
     }
+    if (!RHO && (flags & PIC_F_EMIT_MOVERS)) mb_flush(mb, B);
   } else {
     float acc[NA];
 #pragma unroll
@@ -672,7 +678,7 @@ __device__ __forceinline__ void cell_tile(const KGrid& G, const KBins& B, const 
       if (wave == 0) cv_consume<O, DIM, 0, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       else if (wave == 1) cv_consume<O, DIM, 1, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
       else cv_consume<O, DIM, 2, RHO>(k0, k1, sf, sf + 3 * CV_CAP, acc, last, tb, tw, cur, win);
-      if (!RHO && (flags & (PIC_F_DRIFT | PIC_F_EMIT_MOVERS)))
+      if (drift)
         cv_drift_unit<DIM>(G, B, P, tb, s_off, s_len, cur, tab + ub * CV_TAB, hdt == 0.0f, wave,
                            mb, flags, dt, bad);
       __syncthreads();
