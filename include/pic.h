@@ -72,7 +72,7 @@ enum { PIC_REBIN_FULL = 0, PIC_REBIN_INCREMENTAL = 1, PIC_REBIN_AUTO = 2 };
 
 enum {
   PIC_F_ACCUMULATE = 1u,     /* add into J instead of overwriting it                       */
-  PIC_F_DETERMINISTIC = 2u,  /* reserved; bins are always kept in a deterministic order    */
+                             /* (bit 2u is not used: rejected as an unknown flag)          */
   PIC_F_EMIT_MOVERS = 4u,    /* pic_deposit records particles whose cell no longer matches */
                              /* their bin, for the next PIC_REBIN_INCREMENTAL              */
   PIC_F_DRIFT = 8u,          /* pic_deposit then moves every particle x += v dt (grid dt)  */
@@ -143,7 +143,8 @@ void pic_sort_policy_default(pic_sort_policy* out);
 int pic_policy_decide(const pic_sort_policy* p, int steps_since_sort, int rebuilds_since_sort,
                       double empty_slot_ratio, double perf, double perf_baseline, int* trigger);
 
-/* Create bins for particles stored in arrays of `nslots` slots. tile[3] is the particle
+/* Create bins (the cell-sorted index structure that Alg. 1 keeps per tile, with gapped
+ * per-cell slots as in Sec. 4.3.1) for particles stored in arrays of `nslots` slots. tile[3] is the particle
  * tile (cells per tile per dimension, tile[2] = 1 in 2D). `slack` is the fraction of
  * extra slots a full sort gives every cell (at least one per cell). `max_movers`
  * bounds the mover list (0 = nslots / 8 + 4096). Allocates device memory (synchronous).
@@ -226,7 +227,11 @@ pic_status pic_bins_report_perf(pic_bins* bins, double perf);
  * particle at x +- (dt/2) u / gamma, the offset formed in float32 and added to x in
  * float64, wrapped on periodic dimensions (positions are not changed by it); it is taken by
  * PIC_PATH_AUTO, PIC_PATH_CELL_VALU and PIC_PATH_UNSORTED (UNSUPPORTED on the other
- * paths). */
+ * paths). Repeatability: the per-cell and matrix paths sum in a fixed order, so equal
+ * inputs and bins give bitwise equal J, except for the stencil nodes of a particle found
+ * outside its tile's window (a mover no bin had room for, far from its bin), which go to
+ * J with float atomics; the LDS-atomic and unsorted paths use float atomics throughout.
+ * The bins themselves are always left in a deterministic order by pic_rebin. */
 pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bins* bins,
                        float* Jx, float* Jy, float* Jz, int path, unsigned flags,
                        hipStream_t stream);
@@ -247,7 +252,7 @@ pic_status pic_deposit_noalloc(const pic_grid* grid, pic_particles* p, pic_bins*
 /* Adjoint of pic_deposit for L = sum_c <G_c, J_c>. Writes per slot (gap slots get 0):
  * dL/dx, dL/dy, dL/dz (dz ignored in 2D; may be NULL there), dL/dux, dL/duy, dL/duz and,
  * if dw is not NULL, dL/dw. Shape weights are recomputed, not stored. `bins` may be NULL
- * (particle-parallel gather, no tiles). */
+ * (particle-parallel gather, no tiles). flags must be 0. */
 pic_status pic_deposit_backward(const pic_grid* grid, const pic_particles* p,
                                 const pic_bins* bins, const float* Gx, const float* Gy,
                                 const float* Gz, float* dx, float* dy, float* dz,
@@ -282,9 +287,9 @@ pic_status pic_gather_fields(const pic_grid* grid, const pic_particles* p, pic_b
 /* Particle push: the field gather above, then the relativistic Boris rotation and the move
  * (the push half of the PIC cycle, Sec. 3.1, which the paper's Alg. 1 leaves to the host
  * code). With c = 1 and h = qm dt / 2: u- = u + h E, t = h B / gamma(u-),
- * s = 2 t / (1 + |t|^2), u+ = u- + (u- + u- x t) x s, u <- u+ + h E (float64 arithmetic,
- * stored as float32), then x <- x + dt u / gamma(u) with the operation order and periodic
- * wrap of pic_drift. qm: charge-to-mass ratio of the species; E, B: as for
+ * s = 2 t / (1 + |t|^2), u+ = u- + (u- + u- x t) x s, u <- u+ + h E (float32, like the
+ * stored momenta), then x <- x + dt u / gamma(u) (float64, like the positions) with the
+ * operation order and periodic wrap of pic_drift. qm: charge-to-mass ratio of the species; E, B: as for
  * pic_gather_fields (device, read only). Updates x, y, z, ux, uy, uz of every valid
  * particle in place; gap slots and out-of-domain particles are left alone. With bins the
  * tile windows of the fields are read once into LDS (particles that left their tile are
@@ -317,7 +322,8 @@ pic_status pic_deposit_esirkepov(const pic_grid* grid, const pic_particles* p, p
                                  hipStream_t stream);
 
 /* Constant-velocity move of every valid particle, x += v dt (float64), with periodic
- * wrap: the stand-in for the particle push between steps. */
+ * wrap: the stand-in for the particle push of the PIC cycle (Sec. 3.1; Alg. 1 moves the
+ * particles between depositions). */
 pic_status pic_drift(const pic_grid* grid, pic_particles* p, double dt, hipStream_t stream);
 
 /* ---- batched patches ---------------------------------------------------------------
@@ -371,7 +377,9 @@ int pic_auto_path(const pic_grid* grid, const pic_bins* bins);
 pic_status pic_plan_patch_path(const pic_plan* plan, int patch, int* path);
 
 /* Synchronises `stream` and reports the first device-side error recorded in `bins`
- * (PIC_OK if none); clears the flags. */
+ * (PIC_OK if none); clears the flags. With bins NULL it reports the errors of calls made
+ * without bins. (Device-side errors are the paper's silent cases made explicit: a particle
+ * outside the domain, a non-finite position, bins without room.) */
 pic_status pic_check(pic_bins* bins, hipStream_t stream);
 
 const char* pic_last_error(void);

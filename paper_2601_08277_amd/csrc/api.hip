@@ -489,7 +489,7 @@ pic_status deposit_check_args(const pic_grid* grid, const pic_particles* p, cons
   if (st != PIC_OK) return st;
   if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
   if (!Jx || !Jy || !Jz) return set_error(PIC_ERR_INVALID_ARG, "J pointers must not be NULL");
-  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC | PIC_F_EMIT_MOVERS | PIC_F_DRIFT |
+  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_EMIT_MOVERS | PIC_F_DRIFT |
                           PIC_F_MIDPOINT))
     return set_error(PIC_ERR_INVALID_ARG, "unknown flag bits");
   if (path < PIC_PATH_AUTO || path > PIC_PATH_UNSORTED)
@@ -543,7 +543,7 @@ extern "C" pic_status pic_deposit_rho(const pic_grid* grid, const pic_particles*
   if (st != PIC_OK) return st;
   if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
   if (!rho) return set_error(PIC_ERR_INVALID_ARG, "rho must not be NULL");
-  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC))
+  if (flags & ~(unsigned)PIC_F_ACCUMULATE)
     return set_error(PIC_ERR_INVALID_ARG, "pic_deposit_rho takes PIC_F_ACCUMULATE only");
   if (!b) return set_error(PIC_ERR_INVALID_ARG, "bins required");
   if (!same_grid(*grid, b->grid)) return set_error(PIC_ERR_INVALID_ARG, "grid differs from the bins' grid");
@@ -568,7 +568,7 @@ extern "C" pic_status pic_deposit_backward(const pic_grid* grid, const pic_parti
   if ((st = validate_particles(p, grid->dim)) != PIC_OK) return st;
   if (!Gx || !Gy || !Gz || !dx || !dy || (grid->dim == 3 && !dz) || !dux || !duy || !duz)
     return set_error(PIC_ERR_INVALID_ARG, "gradient pointers must not be NULL");
-  if (flags & ~(unsigned)PIC_F_DETERMINISTIC) return set_error(PIC_ERR_INVALID_ARG, "unknown flag bits");
+  if (flags != 0) return set_error(PIC_ERR_INVALID_ARG, "pic_deposit_backward takes no flags");
   if (b && !same_grid(*grid, b->grid)) return set_error(PIC_ERR_INVALID_ARG, "grid differs from the bins' grid");
   KGrid G = make_kgrid(*grid);
   KPart P = make_kpart(*p);

@@ -158,7 +158,7 @@ extern "C" pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* p
   if (!plan || !particles || !J3) return set_error(PIC_ERR_INVALID_ARG, "NULL argument");
   if (path != PIC_PATH_AUTO && path != PIC_PATH_CELL_VALU)
     return set_error(PIC_ERR_UNSUPPORTED, "batched launches take PIC_PATH_AUTO or PIC_PATH_CELL_VALU");
-  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_DETERMINISTIC | PIC_F_EMIT_MOVERS | PIC_F_DRIFT |
+  if (flags & ~(unsigned)(PIC_F_ACCUMULATE | PIC_F_EMIT_MOVERS | PIC_F_DRIFT |
                           PIC_F_MIDPOINT))
     return set_error(PIC_ERR_INVALID_ARG, "unknown flag bits");
   std::vector<BatchPatch> pd(plan->npatch);

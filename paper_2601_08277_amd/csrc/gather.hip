@@ -300,12 +300,11 @@ extern "C" pic_status pic_gather_fields(const pic_grid* grid, const pic_particle
 // ---------------------------------------------------------------------------------------
 // Particle push: the gather above followed by the relativistic Boris rotation (c = 1,
 // h = qm dt / 2) and the move, one pass over the particles. With u- = u + h E,
-// t = h B / gamma(u-), s = 2 t / (1 + |t|^2): u+ = u- + (u- + u- x t) x s, u <- u+ + h E
-// (rounded to float32), then x moves with the new u exactly as drift_one does. The
-// rotation runs in float64: its cost is small next to the gather and it keeps |u| to
-// float64 rounding through many pushes.
+// t = h B / gamma(u-), s = 2 t / (1 + |t|^2): u+ = u- + (u- + u- x t) x s, u <- u+ + h E,
+// all in float32 like the stored momenta; then x moves with the new u exactly as
+// drift_one does (the position update stays in float64, like the positions).
 
-__device__ __forceinline__ void cross3(const double* a, const double* b, double* r) {
+__device__ __forceinline__ void cross3(const float* a, const float* b, float* r) {
   r[0] = a[1] * b[2] - a[2] * b[1];
   r[1] = a[2] * b[0] - a[0] * b[2];
   r[2] = a[0] * b[1] - a[1] * b[0];
@@ -313,24 +312,22 @@ __device__ __forceinline__ void cross3(const double* a, const double* b, double*
 
 template <int DIM>
 __device__ __forceinline__ void boris_move(const KGrid& G, const KPart& P, int s, const float* v,
-                                           double h, double dt) {
+                                           float h, double dt) {
   // every load before the first store: the arrays may alias, which would keep a later
   // load behind an earlier store
   double pos[3] = {P.x[s], P.y[s], DIM == 3 ? P.z[s] : 0.0};
-  double um[3] = {(double)P.ux[s] + h * (double)v[0], (double)P.uy[s] + h * (double)v[1],
-                  (double)P.uz[s] + h * (double)v[2]};
-  const double gm = __builtin_sqrt(1.0 + ((um[0] * um[0] + um[1] * um[1]) + um[2] * um[2]));
-  const double t[3] = {h * (double)v[3] / gm, h * (double)v[4] / gm, h * (double)v[5] / gm};
-  const double k = 2.0 / (1.0 + ((t[0] * t[0] + t[1] * t[1]) + t[2] * t[2]));
-  const double sv[3] = {k * t[0], k * t[1], k * t[2]};
-  double c[3], up[3];
+  const float um[3] = {P.ux[s] + h * v[0], P.uy[s] + h * v[1], P.uz[s] + h * v[2]};
+  const float ig = 1.0f / __builtin_sqrtf(1.0f + ((um[0] * um[0] + um[1] * um[1]) + um[2] * um[2]));
+  const float t[3] = {h * v[3] * ig, h * v[4] * ig, h * v[5] * ig};
+  const float k = 2.0f / (1.0f + ((t[0] * t[0] + t[1] * t[1]) + t[2] * t[2]));
+  const float sv[3] = {k * t[0], k * t[1], k * t[2]};
+  float c[3], up[3];
   cross3(um, t, c);
 #pragma unroll
   for (int d = 0; d < 3; ++d) up[d] = um[d] + c[d];
   cross3(up, sv, c);
-  const float un[3] = {(float)(um[0] + c[0] + h * (double)v[0]),
-                       (float)(um[1] + c[1] + h * (double)v[1]),
-                       (float)(um[2] + c[2] + h * (double)v[2])};
+  const float un[3] = {um[0] + c[0] + h * v[0], um[1] + c[1] + h * v[1],
+                       um[2] + c[2] + h * v[2]};
   P.ux[s] = un[0];
   P.uy[s] = un[1];
   P.uz[s] = un[2];
@@ -342,7 +339,7 @@ __device__ __forceinline__ void boris_move(const KGrid& G, const KPart& P, int s
 
 // Particle-parallel push from global memory (no bins).
 template <int O, int DIM>
-__global__ __launch_bounds__(256) void k_push(KGrid G, KPart P, FieldPtrs F, double h, double dt,
+__global__ __launch_bounds__(256) void k_push(KGrid G, KPart P, FieldPtrs F, float h, double dt,
                                               uint32_t* err) {
   uint32_t bad = 0;
   const FieldFetch ff{G, F.f, bad};
@@ -365,7 +362,7 @@ __global__ __launch_bounds__(256) void k_push(KGrid G, KPart P, FieldPtrs F, dou
 // valid particle) and are not visited.
 template <int O, int DIM>
 __global__ __launch_bounds__(256) void k_push_tile(KGrid G, KBins B, KPart P, FieldPtrs F,
-                                                   double h, double dt,
+                                                   float h, double dt,
                                                    int32_t* __restrict__ list) {
   extern __shared__ __align__(16) float sF[];
   uint32_t bad = 0;
@@ -407,7 +404,7 @@ __global__ __launch_bounds__(256) void k_push_tile(KGrid G, KBins B, KPart P, Fi
 
 template <int O, int DIM>
 __global__ __launch_bounds__(256) void k_push_list(KGrid G, KBins B, KPart P, FieldPtrs F,
-                                                   double h, double dt,
+                                                   float h, double dt,
                                                    const int32_t* __restrict__ list) {
   uint32_t bad = 0;
   const FieldFetch ff{G, F.f, bad};
@@ -429,7 +426,7 @@ __global__ __launch_bounds__(256) void k_push_list(KGrid G, KBins B, KPart P, Fi
 
 template <int O, int DIM>
 static void launch_push(const KGrid& G, const KPart& P, pic_bins* b, const FieldPtrs& F,
-                        double h, double dt, hipStream_t s) {
+                        float h, double dt, hipStream_t s) {
   const size_t smem = b ? tile_kernel_smem<O, DIM>(b->kb) : 0;
   if (b && b->sorted_once && smem <= b->max_lds) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->kb.ctr + CTR_TOTAL, (int64_t)1);
@@ -464,7 +461,7 @@ extern "C" pic_status pic_push(const pic_grid* grid, pic_particles* p, pic_bins*
   const KGrid G = make_kgrid(*grid);
   const KPart P = make_kpart(*p);
   const FieldPtrs F{{Ex, Ey, Ez, Bx, By, Bz}};
-  const double h = 0.5 * qm * dt;
+  const float h = (float)(0.5 * qm * dt);
 #define PU(O_, D_) launch_push<O_, D_>(G, P, b, F, h, dt, stream)
   if (G.dim == 3) {
     if (G.order == 1) PU(1, 3); else if (G.order == 2) PU(2, 3); else PU(3, 3);

@@ -19,7 +19,7 @@ PATH_AUTO, PATH_ATOMIC, PATH_CELL_VALU, PATH_MFMA_BF16, PATH_MFMA_FP16, PATH_UNS
 PATH_NAMES = {"auto": PATH_AUTO, "atomic": PATH_ATOMIC, "cell_valu": PATH_CELL_VALU,
               "mfma_bf16": PATH_MFMA_BF16, "mfma_fp16": PATH_MFMA_FP16, "unsorted": PATH_UNSORTED}
 REBIN_FULL, REBIN_INCREMENTAL, REBIN_AUTO = 0, 1, 2
-F_ACCUMULATE, F_DETERMINISTIC, F_EMIT_MOVERS, F_DRIFT, F_MIDPOINT = 1, 2, 4, 8, 16
+F_ACCUMULATE, F_EMIT_MOVERS, F_DRIFT, F_MIDPOINT = 1, 4, 8, 16
 INVALID_ID = -1
 
 EXPORTS = ["pic_sort_policy_default", "pic_policy_decide", "pic_bins_create", "pic_bins_destroy",

@@ -179,3 +179,23 @@ def test_tuning_cache_parser(L, tmp_path):
     assert L.pic_tuning_load(str(f).encode()) == pic.PIC_ERR_INVALID_ARG
     assert L.pic_tuning_load(str(tmp_path / "missing.json").encode()) == pic.PIC_ERR_INVALID_ARG
     assert L.pic_tuning_load(None) == pic.PIC_OK
+
+
+def test_unused_flag_bit_is_rejected_without_gpu(L):
+    """Flag bit 2 has no meaning (the bins are always kept in a deterministic order and the
+    repeatability of J depends on the path, see pic.h): every call that takes flags
+    rejects it before looking at bins or launching anything."""
+    from paper_2601_08277_amd import pic
+    g = _grid3(pic)
+    p = _fake_particles(pic)
+    f = ctypes.c_void_p(4096)
+    for path in (pic.PATH_CELL_VALU, pic.PATH_UNSORTED):
+        assert L.pic_deposit(ctypes.byref(g), ctypes.byref(p), None, f, f, f, path, 2,
+                             None) == pic.PIC_ERR_INVALID_ARG
+        assert b"flag" in L.pic_last_error()
+        assert L.pic_deposit_noalloc(ctypes.byref(g), ctypes.byref(p), None, f, f, f, path, 2,
+                                     None) == pic.PIC_ERR_INVALID_ARG
+    assert L.pic_deposit_rho(ctypes.byref(g), ctypes.byref(p), None, f, 2, None) == -1
+    assert L.pic_deposit_backward(ctypes.byref(g), ctypes.byref(p), None, f, f, f, f, f, f, f,
+                                  f, f, None, 2, None) == -1
+    assert b"flags" in L.pic_last_error()

@@ -139,3 +139,36 @@ def test_batched_argument_errors():
     plan.close()
     bins2.close()
     bins3.close()
+
+
+def test_batched_with_tuned_tiles_and_launch_shape():
+    """The C4 recipe at larger edges, each patch binned with the tile the committed tuning
+    cache gives its (order, ppc) and the plan built with the cache's workgroups per compute
+    unit: every patch matches the oracle and the single-patch call bitwise."""
+    import os
+    from paper_2601_08277_amd import autotune, pic
+    cache_path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                              "paper_2601_08277_amd", "tune_cache.json")
+    cache = autotune.load(cache_path)
+    patches = synth.c4_patches(npatch=6, edge=(16, 40), ppc_clip=(1, 40), seed=17)
+    say("case batched tuned tiles")
+    made, tiles = [], []
+    for params, arrays in patches:
+        tile = autotune.lookup(cache, params["order"], params["ppc"])[0]
+        tiles.append(tile)
+        made.append(setup(params, arrays, tile=tile))
+    assert len(set(tiles)) >= 2, tiles         # the cache picks different tiles by class
+    plan = pic.Plan([m[0] for m in made], [m[3] for m in made], tune_cache=cache_path)
+    assert plan.info()["blocks_per_cu"] == min(cache["blocks_per_cu"], plan.info()["blocks_per_cu"])
+    Jb = pic.deposit_batched(plan, [m[2] for m in made], path="cell_valu")
+    torch.cuda.synchronize()
+    for k, ((params, arrays), (grid, og, parts, bins)) in enumerate(zip(patches, made)):
+        Js = pic.deposit(grid, parts, bins, "cell_valu")
+        torch.cuda.synchronize()
+        for c in range(3):
+            assert torch.equal(Jb[k][c], Js[c]), (k, c, tiles[k])
+        want = oracle_J(og, arrays)
+        assert max(rel_l2(Jb[k][c].cpu().numpy(), want[c]) for c in range(3)) <= TOL_FP32
+    plan.close()
+    for m in made:
+        m[3].close()
