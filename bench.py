@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="cells per dimension")
     ap.add_argument("--ppc", type=int, default=8)
     ap.add_argument("--tile", default="8x8x4", help="particle tile, cells (x by y by z)")
-    ap.add_argument("--slack", type=float, default=0.5, help="free slots per bin, per particle")
+    ap.add_argument("--slack", type=float, default=1.0, help="free slots per bin, per particle")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 256x256x1024 LWFA leg")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)

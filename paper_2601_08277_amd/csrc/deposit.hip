@@ -29,6 +29,31 @@ void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 
+// Zero the three current components in one launch (float4 stores where aligned).
+__global__ void k_zero_j3(float* __restrict__ a, float* __restrict__ b, float* __restrict__ c,
+                          int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  float* arr[3] = {a, b, c};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    float* p = arr[k];
+    const int64_t head = (int64_t)((-(((uintptr_t)p) >> 2)) & 3);   // floats before 16-B alignment
+    const int64_t h = head < n ? head : n;
+    for (int64_t i = i0; i < h; i += stride) p[i] = 0.0f;
+    const int64_t nv = (n - h) / 4;
+    float4* q = (float4*)(p + h);
+    for (int64_t i = i0; i < nv; i += stride) q[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int64_t i = h + 4 * nv + i0; i < n; i += stride) p[i] = 0.0f;
+  }
+}
+
+void launch_zero_j3(float* a, float* b, float* c, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n / 4 + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_zero_j3, dim3((unsigned)blocks), dim3(256), 0, s, a, b, c, n);
+}
+
 uint32_t* nobins_err_ptr() {
   static uint32_t* ptr = nullptr;
   if (!ptr) {
@@ -427,9 +452,7 @@ bool deposit_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, floa
                     int path, unsigned flags, double dt, hipStream_t s) {
   int64_t nJ = (int64_t)G.N[0] * G.N[1] * G.N[2];
   if (!(flags & PIC_F_ACCUMULATE)) {
-    launch_fill_f32(J0, nJ, 0.0f, s);
-    launch_fill_f32(J1, nJ, 0.0f, s);
-    launch_fill_f32(J2, nJ, 0.0f, s);
+    launch_zero_j3(J0, J1, J2, nJ, s);
   }
   if (b && (flags & PIC_F_EMIT_MOVERS)) reset_movers(b, s);
   const bool drift = flags & PIC_F_DRIFT;

@@ -493,9 +493,7 @@ extern "C" pic_status pic_deposit_esirkepov(const pic_grid* grid, const pic_part
   for (int d = 0; d < grid->dim; ++d) X.sc[d] = grid->dx[d] / grid->dt;
   const int64_t nJ = (int64_t)G.N[0] * G.N[1] * G.N[2];
   if (!(flags & PIC_F_ACCUMULATE)) {
-    launch_fill_f32(Jx, nJ, 0.0f, stream);
-    launch_fill_f32(Jy, nJ, 0.0f, stream);
-    launch_fill_f32(Jz, nJ, 0.0f, stream);
+    launch_zero_j3(Jx, Jy, Jz, nJ, stream);
   }
 #define ES(O_, D_) launch_esk<O_, D_>(G, P, b, X, Jx, Jy, Jz, stream)
   if (G.dim == 3) {

@@ -132,6 +132,19 @@ __device__ __forceinline__ void set_gap(const KPart& D, int d) {
   D.id[d] = PIC_INVALID_ID;
 }
 
+// Gap slot written in every array, for passes that rewrite whole slot ranges: their lines
+// are then written in full and never read back to merge a partial write.
+__device__ __forceinline__ void set_gap_full(const KPart& D, int d) {
+  D.x[d] = 0.0;
+  D.y[d] = 0.0;
+  D.z[d] = 0.0;
+  D.ux[d] = 0.0f;
+  D.uy[d] = 0.0f;
+  D.uz[d] = 0.0f;
+  D.w[d] = 0.0f;
+  D.id[d] = PIC_INVALID_ID;
+}
+
 __device__ __forceinline__ void swap_slots(const KPart& D, int a, int c) {
   const Payload pa = load_slot(D, a), pc = load_slot(D, c);
   store_slot(D, a, pc);
@@ -306,7 +319,7 @@ __global__ __launch_bounds__(256) void k_full_place(KBins B, KPart P, KPart S,
   for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < P.nslots; d += gridDim.x * blockDim.x) {
     const int j = d < used ? src[d] : -1;
     if (j >= 0) copy_slot(P, d, S, j);
-    else set_gap(P, d);
+    else set_gap_full(P, d);
   }
 }
 
@@ -548,7 +561,7 @@ __global__ __launch_bounds__(256) void k_rebuild(KGrid G, KBins B, KPart P, KPar
     }
     const int k = d - s_new[lo];
     if (k < s_len[lo]) copy_slot(P, d, S, s_off[lo] + k);
-    else set_gap(P, d);
+    else set_gap_full(P, d);
   }
   for (int i = threadIdx.x; i < tb.nb; i += blockDim.x) B.off[tb.b0 + i] = s_new[i];
   if (threadIdx.x == 0) {

@@ -280,14 +280,14 @@ def test_auto_policy_pipelined(which):
 
 def test_timed_step_configuration():
     """The benchmark's step exactly: per-cell VALU path, PIC_F_DRIFT | PIC_F_EMIT_MOVERS
-    (no midpoint), 8x8x4 tiles, slack 0.5, AUTO rebins, on a grid with ragged tiles. Every
+    (no midpoint), 8x8x4 tiles, slack 1.0, AUTO rebins, on a grid with ragged tiles. Every
     step: J within the float32 tolerance of the oracle, positions bitwise equal to the
     oracle's drift, bins equal to the oracle's sets (stale particles only where an insert
     overflowed)."""
     say("case timed-step configuration")
     from paper_2601_08277_amd import pic
     params, arrays = synth.uniform(3, (36, 28, 30), 8, 0.05, 3, seed=1002, dt=0.2)
-    grid, og, parts, bins = setup(params, arrays, tile=(8, 8, 4), slack=0.5)
+    grid, og, parts, bins = setup(params, arrays, tile=(8, 8, 4), slack=1.0)
     pol = pic.policy()
     J = pic.new_J(grid)
     ref = dict(arrays)
