@@ -73,6 +73,10 @@ def parse():
     ap.add_argument("--slack", type=float, default=1.0, help="free slots per bin, per particle")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 256x256x1024 LWFA leg")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle runs in worker processes (full-size check, CPU "
+                         "baseline, LWFA slab check): for profiled runs, whose tool the "
+                         "workers would load too")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c4", "c5"),
                     help="c2: 128^3 uniform step (default); c3: 256x256x1024 LWFA snapshot; "
@@ -202,9 +206,10 @@ def main():
     }
     if not args.no_extras:
         procs = oracle_procs()
-        log(f"full-size check against the oracle ({procs} processes)")
-        out["full_size_check"], full_t = full_size_check(pic, torch, grid, parts, bins, J, path,
-                                                         params, procs)
+        if not args.no_cpu:
+            log(f"full-size check against the oracle ({procs} processes)")
+            out["full_size_check"], full_t = full_size_check(pic, torch, grid, parts, bins, J,
+                                                             path, params, procs)
         log("per-path table, charge density, gather, ablations, midpoint, Esirkepov, cycle")
         out["paths"] = path_table(pic, torch, grid, parts, bins, N, ncell)
         out["charge_density"] = rho_line(pic, torch, grid, parts, bins, N, ncell)
@@ -214,8 +219,9 @@ def main():
         out["esirkepov_deposit"] = esirkepov_line(pic, torch, grid, parts, bins, N, ncell)
         # last: the push moves the snapshot's particles
         out["pic_cycle"] = cycle_line(pic, torch, grid, parts, bins, N, ncell)
-        log("CPU baseline")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, N, full_t, procs)
+        if not args.no_cpu:
+            log("CPU baseline")
+            out["cpu_baseline"] = cpu_baseline(args.cpu_sample, N, full_t, procs)
         bw = copy_bandwidth(torch)
         out["hbm_copy_GBps"] = bw
         out["roofline"]["frac_vs_measured_copy"] = achieved / bw
@@ -224,7 +230,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extras and not args.no_c3:
         log("laser-wakefield-shaped 256x256x1024 leg")
-        out["c3"] = c3_leg(args, torch, pic, synth, oracle_procs())
+        out["c3"] = c3_leg(args, torch, pic, synth, oracle_procs(), check=not args.no_cpu)
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -734,7 +740,7 @@ def _slab_oracle(params, arrays, za, zb, procs):
     return [j[za - lo + ng: zb - lo + ng] for j in J], int(sel.sum())
 
 
-def c3_leg(args, torch, pic, synth, procs):
+def c3_leg(args, torch, pic, synth, procs, check=True):
     """The 256x256x1024 laser-wakefield-shaped snapshot (order 3): static deposition on every
     path (J overwritten), the best path's roofline fraction, and its rel-L2 against the FP64
     oracle on two slabs of z planes (the lower guard boundary and a slab through the
@@ -745,7 +751,7 @@ def c3_leg(args, torch, pic, synth, procs):
     n = params["n"]
     ncell = int(np.prod(n))
     ng = params["ng"]
-    slabs = [(-2, 14), (700, 732)]
+    slabs = [(-2, 14), (700, 732)] if check else []
     log(f"  {N} particles generated; oracle on z-plane slabs {slabs}")
     refs = [_slab_oracle(params, arrays, za, zb, procs) for za, zb in slabs]
     slots = pic.slots_for(N, ncell, 0.25)
@@ -769,7 +775,7 @@ def c3_leg(args, torch, pic, synth, procs):
                 errs.append(float(np.linalg.norm(got - want[c]) / np.linalg.norm(want[c])))
         res[name] = {"kernel_ms": ms, "particles_per_s": N / (ms * 1e-3),
                      "hbm_frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "rel_l2_vs_oracle_z_slabs": max(errs)}
+                     "rel_l2_vs_oracle_z_slabs": max(errs) if errs else None}
     bins.check()
     bins.close()
     best = min(res, key=lambda k: res[k]["kernel_ms"])

@@ -448,7 +448,10 @@ __global__ __launch_bounds__(256) void k_compact(KBins B, KPart P) {
     const int I = min(ins, cap - L);
     if (I >= 2) sort_range_by_id(P, o + L, I);
     const int total = L + I;
-    if (total <= 16) {
+    if (outf == 0) {
+      // nothing left: no holes, the inserted particles extend the dense prefix
+      B.len[b] = total;
+    } else if (total <= 16) {
       // ids read at once (independent loads), holes and sources as bit masks
       int32_t ids[16];
 #pragma unroll
