@@ -229,7 +229,7 @@ extern "C" pic_status pic_bins_create(const pic_grid* grid, const int tile[3], d
   A(dalloc(&b->kb.mv_new, max_movers));
   A(dalloc(&b->bin_cell, nbins));
   A(dalloc(&b->sbin, nslots));
-  A(dalloc(&b->dctr, 1));
+  A(dalloc(&b->dctr, 2));
   {
     int64_t wm = 1;
     for (int d = 0; d < grid->dim; ++d) wm *= T[d] + 4;
@@ -282,7 +282,7 @@ extern "C" pic_status pic_bins_create(const pic_grid* grid, const int tile[3], d
   A(hipMemset(b->kb.out_flag, 0, (size_t)nbins * sizeof(int32_t)));
   A(hipMemset(b->kb.ins_cnt, 0, (size_t)nbins * sizeof(int32_t)));
   A(hipMemset(b->kb.tile_flag, 0, (size_t)ntiles * sizeof(int32_t)));
-  A(hipMemset(b->dctr, 0, sizeof(CtrBlock)));
+  A(hipMemset(b->dctr, 0, 2 * sizeof(CtrBlock)));
   memset(b->hstats, 0, sizeof(CtrBlock) * STATS_RING);
   A(hipDeviceSynchronize());
   if (e != hipSuccess) {
@@ -430,14 +430,14 @@ extern "C" pic_status pic_rebin(const pic_grid* grid, pic_particles* p, pic_bins
   }
   if (b->history.empty()) b->history_base = seq;
   b->history.push_back(rec);
-  // statistics: device counters -> this call's pinned ring slot, read later in call order
+  // statistics: device counters (snapshot) -> this call's pinned ring slot, read later in
+  // call order; the per-rebin counters restart from zero in the same kernel
   const int slot = (int)(seq % STATS_RING);
   rebin_finish(b, stream);
-  HIP_TRY(hipMemcpyAsync(&b->hstats[slot], b->dctr, sizeof(CtrBlock), hipMemcpyDeviceToHost,
+  HIP_TRY(hipMemcpyAsync(&b->hstats[slot], b->dctr + 1, sizeof(CtrBlock), hipMemcpyDeviceToHost,
                          stream));
   HIP_TRY(hipEventRecord(b->stats_ev[slot], stream));
   b->seq_enqueued = seq + 1;
-  reset_step_counters(b, stream);
   return check_hip(hipGetLastError(), "pic_rebin launch");
 }
 

@@ -29,11 +29,16 @@ void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 
-// Zero the three current components in one launch (float4 stores where aligned).
+// Zero the three current components in one launch (float4 stores where aligned) and, when
+// given, the bins' mover counters.
 __global__ void k_zero_j3(float* __restrict__ a, float* __restrict__ b, float* __restrict__ c,
-                          int64_t n) {
+                          int64_t n, int32_t* __restrict__ ctr) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (ctr && i0 == 0) {
+    ctr[CTR_NMOV] = 0;
+    ctr[CTR_NDROP] = 0;
+  }
   float* arr[3] = {a, b, c};
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -48,10 +53,10 @@ __global__ void k_zero_j3(float* __restrict__ a, float* __restrict__ b, float* _
   }
 }
 
-void launch_zero_j3(float* a, float* b, float* c, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
+void launch_zero_j3(float* a, float* b, float* c, int64_t n, hipStream_t s, int32_t* ctr) {
+  if (n <= 0 && !ctr) return;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n / 4 + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_zero_j3, dim3((unsigned)blocks), dim3(256), 0, s, a, b, c, n);
+  hipLaunchKernelGGL(k_zero_j3, dim3((unsigned)blocks), dim3(256), 0, s, a, b, c, n, ctr);
 }
 
 uint32_t* nobins_err_ptr() {
@@ -451,10 +456,9 @@ static bool launch_tile_atomic(const KGrid& G, const KPart& P, pic_bins* b, floa
 bool deposit_launch(const KGrid& G, const KPart& P, pic_bins* b, float* J0, float* J1, float* J2,
                     int path, unsigned flags, double dt, hipStream_t s) {
   int64_t nJ = (int64_t)G.N[0] * G.N[1] * G.N[2];
-  if (!(flags & PIC_F_ACCUMULATE)) {
-    launch_zero_j3(J0, J1, J2, nJ, s);
-  }
-  if (b && (flags & PIC_F_EMIT_MOVERS)) reset_movers(b, s);
+  const bool emit = b && (flags & PIC_F_EMIT_MOVERS);
+  if (!(flags & PIC_F_ACCUMULATE)) launch_zero_j3(J0, J1, J2, nJ, s, emit ? b->kb.ctr : nullptr);
+  else if (emit) reset_movers(b, s);
   const bool drift = flags & PIC_F_DRIFT;
   if (!b) {
     uint32_t* err = nobins_err_ptr();

@@ -34,7 +34,7 @@ struct pic_bins {
   // device buffers owned by the bins
   int32_t* bin_cell = nullptr;
   int32_t* sbin = nullptr;          // full sort: bin of every slot
-  CtrBlock* dctr = nullptr;
+  CtrBlock* dctr = nullptr;         // [0] live counters, [1] snapshot at the end of a rebin
   KPart scratch{};                  // full sort / rebuild staging, nslots slots
   // scan temporaries (levels of block sums)
   int32_t* scan_tmp[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -80,7 +80,6 @@ void backward_launch(const KGrid& G, const KPart& P, const pic_bins* b, const fl
                      float* dux, float* duy, float* duz, float* dw, hipStream_t s);
 void scan_exclusive_i32(pic_bins* b, int32_t* data, int64_t n, hipStream_t s);
 void reset_movers(pic_bins* b, hipStream_t s);
-void reset_step_counters(pic_bins* b, hipStream_t s);
 
 // Argument checks shared by the entry points (api.hip).
 pic_status validate_grid(const pic_grid* g);

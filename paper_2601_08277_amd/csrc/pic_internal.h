@@ -285,4 +285,5 @@ __device__ __forceinline__ int wave_append(bool pred, int32_t* counter) {
 // Host-side launch helpers implemented in the .hip files.
 struct pic_bins_impl;
 void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
-void launch_zero_j3(float* a, float* b, float* c, int64_t n, hipStream_t s);
+void launch_zero_j3(float* a, float* b, float* c, int64_t n, hipStream_t s,
+                    int32_t* ctr = nullptr);

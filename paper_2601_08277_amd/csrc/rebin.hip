@@ -591,10 +591,17 @@ void rebin_incremental(pic_bins* b, const KGrid& G, const KPart& P, hipStream_t 
 }
 
 // ---- statistics and counters -------------------------------------------------------
-__global__ void k_rebin_finish(KBins B, CtrBlock* c) {
+// End of a rebin: the counters as they stand go to the snapshot block (which the host
+// copies), then the per-rebin ones restart from zero for the next step.
+__global__ void k_rebin_finish(KBins B, CtrBlock* c, CtrBlock* snap) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     B.ctr[CTR_NMOV_LAST] = min(B.ctr[CTR_NMOV], B.max_movers);
     c->cap_used = B.off[B.nbins];
+    *snap = *c;
+    B.ctr[CTR_NMOV] = 0;
+    B.ctr[CTR_NDROP] = 0;
+    B.ctr[CTR_NOVF] = 0;
+    B.ctr[CTR_NREB] = 0;
   }
 }
 
@@ -610,13 +617,11 @@ __global__ void k_reset_step(KBins B, int all) {
 }
 
 void rebin_finish(pic_bins* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_rebin_finish, dim3(1), dim3(64), 0, s, b->kb, b->dctr);
+  hipLaunchKernelGGL(k_rebin_finish, dim3(1), dim3(64), 0, s, b->kb, b->dctr, b->dctr + 1);
 }
 
 void reset_movers(pic_bins* b, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_step, dim3(1), dim3(64), 0, s, b->kb, 0);
 }
 
-void reset_step_counters(pic_bins* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_step, dim3(1), dim3(64), 0, s, b->kb, 1);
-}
+
