@@ -49,10 +49,30 @@ __device__ __forceinline__ void pad_w(const float* w, int s, float* out) {
   }
 }
 
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+// Inclusive scan of v over the wave's 64 lanes with DPP moves: shifts by 1, 2, 4 and 8
+// lanes inside each 16-lane row, then lane 15 of rows 0 and 2 added into rows 1 and 3 and
+// lane 31 into rows 2 and 3. VALU only (a lane shuffle is an LDS round trip); all 64 lanes
+// must be active. `id` is the identity of `op`.
+struct DppAdd {
+  __device__ int operator()(int a, int b) const { return a + b; }
+};
+struct DppMax {
+  __device__ int operator()(int a, int b) const { return a > b ? a : b; }
+};
+template <typename Op>
+__device__ __forceinline__ int wave_scan(int v, int id, Op op) {
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x142, 0xa, 0xf, false));   // row_bcast:15
+  v = op(v, __builtin_amdgcn_update_dpp(id, v, 0x143, 0xc, 0xf, false));   // row_bcast:31
   return v;
+}
+
+// Wave-uniform maximum of a non-negative v.
+__device__ __forceinline__ int wave_max(int v) {
+  return __builtin_amdgcn_readlane(wave_scan(v, 0, DppMax()), PIC_WAVE - 1);
 }
 
 constexpr int CV_GROUP = 64;    // cells per group (lanes)
@@ -118,9 +138,7 @@ struct CellGroup {
 };
 
 __device__ __forceinline__ int wave_sum(int v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  return __builtin_amdgcn_readlane(wave_scan(v, 0, DppAdd()), PIC_WAVE - 1);
 }
 
 // Per-lane count and staged start of the next unit of the group (wave reductions and a scan
@@ -140,15 +158,10 @@ __device__ __forceinline__ void cv_unit_fields(CellGroup& gr, int lane) {
     k = lo;
   }
   const int m = min(r, k);
-  int incl = m;
-#pragma unroll
-  for (int off = 1; off < PIC_WAVE; off <<= 1) {
-    const int t = __shfl_up(incl, off);
-    if (lane >= off) incl += t;
-  }
+  const int incl = wave_scan(m, 0, DppAdd());
   gr.m = m;
   gr.ust = incl - m;
-  gr.nunit = __shfl(incl, PIC_WAVE - 1);
+  gr.nunit = __builtin_amdgcn_readlane(incl, PIC_WAVE - 1);
   gr.last = gr.nunit == rtot;
 }
 
