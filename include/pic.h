@@ -228,9 +228,11 @@ pic_status pic_bins_report_perf(pic_bins* bins, double perf);
  * float64, wrapped on periodic dimensions (positions are not changed by it); it is taken by
  * PIC_PATH_AUTO, PIC_PATH_CELL_VALU and PIC_PATH_UNSORTED (UNSUPPORTED on the other
  * paths). Repeatability: the per-cell and matrix paths sum in a fixed order, so equal
- * inputs and bins give bitwise equal J, except for the stencil nodes of a particle found
- * outside its tile's window (a mover no bin had room for, far from its bin), which go to
- * J with float atomics; the LDS-atomic and unsorted paths use float atomics throughout.
+ * inputs and bins give bitwise equal J, except for stencil nodes outside the tile's
+ * window, which go to J with float atomics; only a particle whose cell lies outside its
+ * bin's tile has such nodes (a mover no bin had room for, or a particle moved across a
+ * tile boundary without a rebin). The LDS-atomic and unsorted paths use float atomics
+ * throughout.
  * The bins themselves are always left in a deterministic order by pic_rebin. */
 pic_status pic_deposit(const pic_grid* grid, pic_particles* p, pic_bins* bins,
                        float* Jx, float* Jy, float* Jz, int path, unsigned flags,
