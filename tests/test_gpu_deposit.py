@@ -209,3 +209,40 @@ def test_cell_paths_bitwise_repeatable():
             assert max(errs) <= TOL_SPLIT, errs
         bins.check()
         bins.close()
+
+
+def test_unit_cap_boundaries():
+    """Units at the 512-particle stage capacity: single cells with 511, 512 and 513
+    particles (one unit of a whole cell, then a second unit of one), a 64-cell group with
+    exactly 8 per cell (512, one unit) and one with 9 per cell (cut at 8, then 1), and
+    empty groups between them; per-cell and split-matrix paths and the charge density
+    against the oracle."""
+    from paper_2601_08277_amd import pic
+    from oracle import deposit as od
+    say("case unit cap boundaries")
+    rng = np.random.default_rng(23)
+    n = (8, 8, 16)                       # four tiles of 8 x 8 x 4, z-planes of 64 cells
+    counts = np.zeros(n[::-1], dtype=np.int64)
+    counts[1, 2, 3], counts[1, 5, 6], counts[1, 7, 0] = 511, 512, 513   # plane 1
+    counts[4, :, :] = 8                  # plane 4: 512 in the group
+    counts[9, :, :] = 9                  # plane 9: 576, cut across the cells
+    counts[14, :, :] = rng.poisson(8.0, size=(8, 8))
+    counts = counts.reshape(-1)
+    x, y, z = synth._place(rng, 3, n, counts)
+    u = [rng.normal(0, 0.2, x.size) for _ in range(3)]
+    arrays = synth._finish(rng, x, y, z, u)
+    params = synth._params(3, n, 3, -1.0, (0, 0, 0), 0, 0.2)
+    grid, og, parts, bins = setup(params, arrays, tile=(8, 8, 4), slack=0.5)
+    want = oracle_J(og, arrays)
+    for path in ("cell_valu", "mfma_fp16"):
+        J = pic.deposit(grid, parts, bins, path)
+        torch.cuda.synchronize()
+        tol = TOL_SPLIT if path.startswith("mfma") else TOL_FP32
+        errs = [rel_l2(J[c].cpu().numpy(), want[c]) for c in range(3)]
+        assert max(errs) <= tol, (path, errs)
+    rho = pic.deposit_rho(grid, parts, bins)
+    torch.cuda.synchronize()
+    wr = od.deposit_rho(og, [arrays["x"], arrays["y"], arrays["z"]], arrays["w"])
+    assert rel_l2(rho.cpu().numpy(), wr) <= TOL_FP32
+    bins.check()
+    bins.close()
