@@ -245,13 +245,19 @@ void batched_prologue_launch(const BatchPatch* pd, int npatch, int64_t max_nodes
 // three positions away are examined. Each stored node is written by exactly one workgroup.
 // RHO: the three window copies of the charge density are summed into J0.
 constexpr int HALO_MAXC = 6;      // candidate windows per dimension
+constexpr int HALO_GX = 4;        // tiles along x per workgroup of the single-grid window sum
 
+// The workgroup owns the nodes of gx consecutive tiles along x starting at `tile` (a row
+// of tiles: J is then read and written in whole lines); a node's candidate windows and
+// their order do not depend on gx.
 template <int O, int DIM, bool RHO>
 __device__ __forceinline__ void halo_tile_body(const KGrid& G, const KBins& B,
                                                float* __restrict__ J0, float* __restrict__ J1,
-                                               float* __restrict__ J2, int tile, int32_t* sh) {
+                                               float* __restrict__ J2, int tile, int gx,
+                                               int32_t* sh) {
   constexpr int LO = TileWin<O, DIM>::LO, R = TileWin<O, DIM>::R;
   const TileBox tb = tile_box(G.n, B.T, B.nt, tile);
+  const TileBox tl = tile_box(G.n, B.T, B.nt, tile + gx - 1);   // last tile of the row
   int tcoord[3];
   {
     int t = tile;
@@ -269,11 +275,12 @@ __device__ __forceinline__ void halo_tile_body(const KGrid& G, const KBins& B,
       a[d] = 0;
       len[d] = 1;
     } else {
+      const int last = d == 0 ? tcoord[0] + gx - 1 : tcoord[d];
       a[d] = tb.c0[d];
-      int b = tb.c0[d] + tb.e[d];
+      int b = tl.c0[d] + tl.e[d];
       if (!G.per[d]) {
         if (tcoord[d] == 0) a[d] = tb.c0[d] + LO;
-        if (tcoord[d] == B.nt[d] - 1) b = tb.c0[d] + tb.e[d] + R + LO;
+        if (last == B.nt[d] - 1) b = tl.c0[d] + tl.e[d] + R + LO;
       }
       len[d] = b - a[d];
     }
@@ -296,7 +303,7 @@ __device__ __forceinline__ void halo_tile_body(const KGrid& G, const KBins& B,
       s_W[i * HALO_MAXC] = 1;
       cnt = 1;
     } else {
-      for (int k = -3; k <= 3; ++k) {
+      for (int k = -3; k <= 3 + (d == 0 ? gx - 1 : 0); ++k) {
         int tn = tcoord[d] + k;
         int shift = 0;
         if (tn < 0 || tn >= B.nt[d]) {
@@ -356,7 +363,12 @@ __global__ __launch_bounds__(256) void k_halo_tile(KGrid G, KBins B, float* __re
                                                    float* __restrict__ J1,
                                                    float* __restrict__ J2) {
   extern __shared__ __align__(16) int32_t sh[];
-  halo_tile_body<O, DIM, RHO>(G, B, J0, J1, J2, xcd_tile(blockIdx.x, gridDim.x), sh);
+  // workgroup -> row of up to HALO_GX tiles along x (rows in the tiles' XCD order)
+  const int ngx = (B.nt[0] + HALO_GX - 1) / HALO_GX;
+  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  const int gxi = g % ngx, rest = g / ngx;
+  const int t0 = gxi * HALO_GX + B.nt[0] * rest;
+  halo_tile_body<O, DIM, RHO>(G, B, J0, J1, J2, t0, min(HALO_GX, B.nt[0] - gxi * HALO_GX), sh);
 }
 
 // Batched window sum: one workgroup per (patch, tile) work item of the plan.
@@ -366,9 +378,9 @@ __global__ __launch_bounds__(256) void k_batched_halo_tile(const BatchPatch* __r
   const int pi = __builtin_amdgcn_readfirstlane(items[blockIdx.x].x);
   const int tile = __builtin_amdgcn_readfirstlane(items[blockIdx.x].y);
   const BatchPatch& d = pd[pi];
-  if (d.G.order == 1) halo_tile_body<1, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, sh);
-  else if (d.G.order == 2) halo_tile_body<2, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, sh);
-  else halo_tile_body<3, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, sh);
+  if (d.G.order == 1) halo_tile_body<1, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, 1, sh);
+  else if (d.G.order == 2) halo_tile_body<2, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, 1, sh);
+  else halo_tile_body<3, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, 1, sh);
 }
 
 size_t halo_smem_bytes(const KBins& kb) {
@@ -386,10 +398,13 @@ template <int O, int DIM, bool RHO>
 static void launch_halo_tile(const KGrid& G, pic_bins* b, float* J0, float* J1, float* J2,
                              hipStream_t s) {
   int tot = 0;
-  for (int d = 0; d < 3; ++d) tot += d < DIM ? b->kb.T[d] + TileWin<O, DIM>::R : 1;
+  for (int d = 0; d < 3; ++d)
+    tot += d < DIM ? (d == 0 ? HALO_GX : 1) * b->kb.T[d] + TileWin<O, DIM>::R : 1;
   const size_t smem = (size_t)tot * (1 + 3 * HALO_MAXC) * sizeof(int32_t);
-  hipLaunchKernelGGL((k_halo_tile<O, DIM, RHO>), dim3(b->kb.ntiles), dim3(256), smem, s, G,
-                     b->kb, J0, J1, J2);
+  const int ngx = (b->kb.nt[0] + HALO_GX - 1) / HALO_GX;
+  const int groups = ngx * b->kb.nt[1] * b->kb.nt[2];
+  hipLaunchKernelGGL((k_halo_tile<O, DIM, RHO>), dim3(groups), dim3(256), smem, s, G, b->kb,
+                     J0, J1, J2);
 }
 
 void halo_rho_launch(const KGrid& G, pic_bins* b, float* rho, hipStream_t s) {
