@@ -30,6 +30,10 @@ struct pic_plan {
   int nitems = 0;
   int2* d_items_vec = nullptr;       // tiles of the patches AUTO runs on the per-cell path
   int nitems_vec = 0;
+  int2* d_rows = nullptr;            // window sum: (patch, first tile of a row of tiles)
+  int nrows = 0;
+  int2* d_rows_vec = nullptr;        // the same for the per-cell patches
+  int nrows_vec = 0;
   std::vector<int> patch_path;       // PIC_PATH_AUTO's choice per patch (at plan creation)
   int* d_queue = nullptr;
   size_t smem = 0;
@@ -63,6 +67,8 @@ static void plan_free(pic_plan* p) {
   if (p->h_pd) (void)hipHostFree(p->h_pd);
   if (p->d_items) (void)hipFree(p->d_items);
   if (p->d_items_vec) (void)hipFree(p->d_items_vec);
+  if (p->d_rows) (void)hipFree(p->d_rows);
+  if (p->d_rows_vec) (void)hipFree(p->d_rows_vec);
   if (p->d_queue) (void)hipFree(p->d_queue);
   if (p->upload_ev) (void)hipEventDestroy(p->upload_ev);
   delete p;
@@ -122,6 +128,19 @@ extern "C" pic_status pic_plan_create(const pic_grid* grids, int npatch, pic_bin
     if (p->patch_path[items[i].patch] == PIC_PATH_CELL_VALU) h_vec.push_back(h_items[i]);
   }
   p->nitems_vec = (int)h_vec.size();
+  // window-sum items: rows of up to halo_row_tiles() tiles along x
+  std::vector<int2> h_rows, h_rows_vec;
+  const int gxr = halo_row_tiles();
+  for (int k = 0; k < npatch; ++k) {
+    const KBins& kb = bins[k]->kb;
+    for (int r = 0; r < kb.nt[1] * kb.nt[2]; ++r)
+      for (int x = 0; x < kb.nt[0]; x += gxr) {
+        h_rows.push_back(make_int2(k, x + kb.nt[0] * r));
+        if (p->patch_path[k] == PIC_PATH_CELL_VALU) h_rows_vec.push_back(h_rows.back());
+      }
+  }
+  p->nrows = (int)h_rows.size();
+  p->nrows_vec = (int)h_rows_vec.size();
   int dev = 0, ncu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -131,6 +150,13 @@ extern "C" pic_status pic_plan_create(const pic_grid* grids, int npatch, pic_bin
   if (e == hipSuccess) e = hipMalloc(&p->d_items_vec, sizeof(int2) * std::max<size_t>(h_vec.size(), 1));
   if (e == hipSuccess && !h_vec.empty())
     e = hipMemcpy(p->d_items_vec, h_vec.data(), sizeof(int2) * h_vec.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_rows, sizeof(int2) * std::max<size_t>(h_rows.size(), 1));
+  if (e == hipSuccess) e = hipMalloc(&p->d_rows_vec, sizeof(int2) * std::max<size_t>(h_rows_vec.size(), 1));
+  if (e == hipSuccess && !h_rows.empty())
+    e = hipMemcpy(p->d_rows, h_rows.data(), sizeof(int2) * h_rows.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !h_rows_vec.empty())
+    e = hipMemcpy(p->d_rows_vec, h_rows_vec.data(), sizeof(int2) * h_rows_vec.size(),
+                  hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMalloc(&p->d_queue, sizeof(int) * 4);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->upload_ev, hipEventDisableTiming);
   if (e == hipSuccess)
@@ -212,7 +238,8 @@ extern "C" pic_status pic_deposit_batched(pic_plan* plan, const pic_particles* p
   if (nitems > 0) {
     batched_cell_launch(plan->d_pd, items, nitems, plan->d_queue, plan->blocks, plan->smem, flags,
                         stream);
-    batched_halo_tile_launch(plan->d_pd, items, nitems, plan->halo_smem, stream);
+    batched_halo_tile_launch(plan->d_pd, split ? plan->d_rows_vec : plan->d_rows,
+                             split ? plan->nrows_vec : plan->nrows, plan->halo_smem, stream);
   }
   if (split) {
     // patches on a matrix path: their own launches, J already cleared by the prologue

@@ -371,23 +371,27 @@ __global__ __launch_bounds__(256) void k_halo_tile(KGrid G, KBins B, float* __re
   halo_tile_body<O, DIM, RHO>(G, B, J0, J1, J2, t0, min(HALO_GX, B.nt[0] - gxi * HALO_GX), sh);
 }
 
-// Batched window sum: one workgroup per (patch, tile) work item of the plan.
+// Batched window sum: one workgroup per (patch, first tile of a row of up to HALO_GX tiles
+// along x) item of the plan.
 __global__ __launch_bounds__(256) void k_batched_halo_tile(const BatchPatch* __restrict__ pd,
                                                            const int2* __restrict__ items) {
   extern __shared__ __align__(16) int32_t sh[];
   const int pi = __builtin_amdgcn_readfirstlane(items[blockIdx.x].x);
   const int tile = __builtin_amdgcn_readfirstlane(items[blockIdx.x].y);
   const BatchPatch& d = pd[pi];
-  if (d.G.order == 1) halo_tile_body<1, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, 1, sh);
-  else if (d.G.order == 2) halo_tile_body<2, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, 1, sh);
-  else halo_tile_body<3, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, 1, sh);
+  const int gx = min(HALO_GX, d.B.nt[0] - tile % d.B.nt[0]);
+  if (d.G.order == 1) halo_tile_body<1, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, gx, sh);
+  else if (d.G.order == 2) halo_tile_body<2, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, gx, sh);
+  else halo_tile_body<3, 3, false>(d.G, d.B, d.J[0], d.J[1], d.J[2], tile, gx, sh);
 }
 
 size_t halo_smem_bytes(const KBins& kb) {
   int tot = 0;
-  for (int d = 0; d < 3; ++d) tot += kb.T[d] + 4;
+  for (int d = 0; d < 3; ++d) tot += (d == 0 ? HALO_GX : 1) * kb.T[d] + 4;
   return (size_t)tot * (1 + 3 * HALO_MAXC) * sizeof(int32_t);
 }
+
+int halo_row_tiles() { return HALO_GX; }
 
 void batched_halo_tile_launch(const BatchPatch* pd, const int2* items, int nitems, size_t smem,
                               hipStream_t s) {

@@ -168,6 +168,7 @@ void batched_cell_launch(const BatchPatch* pd, const int2* items, int nitems, in
 void batched_prologue_launch(const BatchPatch* pd, int npatch, int64_t max_nodes, int* queue,
                              unsigned flags, hipStream_t s);
 size_t halo_smem_bytes(const KBins& kb);
+int halo_row_tiles();   // tiles along x summed by one window-sum workgroup
 void batched_halo_tile_launch(const BatchPatch* pd, const int2* items, int nitems, size_t smem,
                               hipStream_t s);
 
